@@ -1,0 +1,191 @@
+/*
+ * vg.h -- C ABI of the MI355X (gfx950) volume-potential library.
+ *
+ * The library computes the volume potential of the Introduction of Vico,
+ * Greengard and Ferrando, "Fast convolution with free-space Green's functions":
+ *
+ *     phi(x) = int_D g_k(x - y) f(y) dy,     D = [-1/2, 1/2]^d,  d in {2, 3},
+ *
+ * with g_k the free-space Laplace kernel (k = 0: 1/(4 pi r) in 3D,
+ * -(1/2 pi) log r in 2D) or Helmholtz kernel (e^{ikr}/(4 pi r) in 3D,
+ * (i/4) H_0^(1)(k r) in 2D, Table 2), by the truncated-kernel method:
+ *   - plan time (Sections 2 and 4): the Fourier transform of the kernel
+ *     truncated at radius L (Tables 1 and 2) is sampled in FP64 on the
+ *     P N-per-axis lattice, inverse transformed into the discrete operator T
+ *     (the response to a unit density at one grid point), and T is transformed
+ *     over the (2N)^d box into the table Khat used by every apply;
+ *   - apply time (Section 4): phi_{i'} = sum_i T(i' - i) f_i, evaluated as
+ *     zero padding to (2N)^d, forward FFT, multiplication by Khat, inverse FFT
+ *     and cropping, in hand-written HIP kernels;
+ *   - gradient (abstract, Section 3): one more inverse FFT per component after
+ *     multiplying the spectrum by i kappa_j.
+ *
+ * Grid and layout (Section 4).  h = 1/N with N even; along every axis array
+ * index a in [0, N) is the point x_a = (a - N/2 + 1) h.  Densities and
+ * potentials are dense C-ordered arrays of N^d interleaved complex numbers
+ * (x_1 slowest, x_d fastest): float2 {re, im} for FP32 plans, double2 for FP64
+ * plans.  phi_{i'} = sum_i T(i' - i) f_i already carries the quadrature weight
+ * h^d.  The sign convention is phi = g * f, i.e. (Delta + k^2) phi = -f.
+ *
+ * Memory.  Every array argument of the apply calls is a DEVICE pointer on the
+ * current HIP device and is owned by the caller; the library owns its plan
+ * tables.  `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ * Apply calls are asynchronous on `stream`; faults inside kernels surface at the
+ * caller's next synchronisation.  Plans are immutable after creation and may be
+ * used from several threads, except that calls passing workspace == NULL share
+ * the plan's internal workspace and must not overlap in time.
+ *
+ * Errors.  Every call returns a vg_status; no C++ exception crosses the ABI.
+ * vg_last_error() returns a thread-local message describing the last failure on
+ * the calling thread.
+ */
+#ifndef VG_H
+#define VG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum vg_status {
+    VG_OK = 0,
+    VG_ERR_INVALID_ARG = 1,      /* bad dimension, size, kernel, k, pointer, option */
+    VG_ERR_UNSUPPORTED_SIZE = 2, /* 2N has a prime factor above 7, or exceeds a limit */
+    VG_ERR_OUT_OF_MEMORY = 3,    /* device or host allocation failed */
+    VG_ERR_NO_DEVICE = 4,        /* no HIP device is visible */
+    VG_ERR_DEVICE = 5,           /* a HIP runtime call or kernel launch failed */
+    VG_ERR_NOT_CAPTURABLE = 6,   /* the call cannot run inside stream capture */
+    VG_ERR_INTERNAL = 7          /* a bug: please report */
+} vg_status;
+
+typedef enum vg_kernel {
+    VG_LAPLACE = 0,   /* Delta:        1/(4 pi r) (3D),  -(1/2 pi) log r (2D) */
+    VG_HELMHOLTZ = 1  /* Delta + k^2:  e^{ikr}/(4 pi r) (3D), (i/4) H_0^(1)(kr) (2D) */
+} vg_kernel;
+
+typedef enum vg_precision {
+    VG_FP32 = 0,  /* complex64 densities and FFTs; tables built in FP64, rounded once */
+    VG_FP64 = 1   /* complex128 end to end */
+} vg_precision;
+
+typedef enum vg_tune_mode {
+    VG_TUNE_OFF = 0,    /* built-in launch shapes */
+    VG_TUNE_QUICK = 1,  /* time a few candidate shapes per pass at plan time */
+    VG_TUNE_FULL = 2    /* time every candidate shape */
+} vg_tune_mode;
+
+typedef struct vg_plan vg_plan;
+
+/* Plan options (vg_plan_create_ex).  Zero-initialised fields take defaults. */
+typedef struct vg_plan_opts {
+    int precision;       /* vg_precision, default VG_FP32 */
+    double L;            /* truncation radius, must exceed sqrt(d); 0 -> 1.8 (3D), 1.5 (2D) (Section 2) */
+    int P;               /* precompute oversampling, must satisfy P > 1 + L; 0 -> 4 (Section 2) */
+    int tune;            /* vg_tune_mode, default VG_TUNE_OFF */
+    int keep_operator;   /* nonzero: keep T (FP64) on the device for vg_plan_operator_entries */
+    void* stream;        /* hipStream_t for the precompute, NULL = null stream */
+} vg_plan_opts;
+
+/* Plan description returned by vg_plan_get_info. */
+typedef struct vg_plan_info {
+    int d, N;
+    int kernel;          /* vg_kernel */
+    int precision;       /* vg_precision */
+    double k, L;
+    int P;
+    double precompute_ms;     /* device time of the FP64 precompute (kernel spectrum -> T -> Khat) */
+    size_t table_bytes;       /* bytes of the Khat octant kept for applies */
+    size_t workspace_bytes;   /* vg_workspace_size */
+    size_t gradient_workspace_bytes;
+} vg_plan_info;
+
+/*
+ * Create a plan for d in {2, 3}, even N >= 4, kernel in {VG_LAPLACE,
+ * VG_HELMHOLTZ}.  Helmholtz needs a finite k > 0 (Laplace ignores k).
+ * Runs the FP64 precompute of Sections 2 and 4 on the current device and
+ * synchronises before returning.
+ * Errors: VG_ERR_INVALID_ARG (bad arguments; *out untouched),
+ * VG_ERR_UNSUPPORTED_SIZE (2N has a prime factor above 7), VG_ERR_NO_DEVICE,
+ * VG_ERR_OUT_OF_MEMORY, VG_ERR_DEVICE.  On error *out is set to NULL.
+ */
+vg_status vg_plan_create(int d, int N, vg_kernel kernel, double k, vg_plan** out);
+vg_status vg_plan_create_ex(int d, int N, vg_kernel kernel, double k,
+                            const vg_plan_opts* opts, vg_plan** out);
+
+/* Release a plan and everything it owns.  NULL is a no-op.  The caller must
+ * ensure no apply using the plan is still running. */
+void vg_plan_destroy(vg_plan* plan);
+
+/* Fill *info.  Errors: VG_ERR_INVALID_ARG for NULL arguments. */
+vg_status vg_plan_get_info(const vg_plan* plan, vg_plan_info* info);
+
+/* Bytes of device workspace an apply / gradient call needs when it is given an
+ * explicit workspace (0 for a NULL plan). */
+size_t vg_workspace_size(const vg_plan* plan);
+size_t vg_gradient_workspace_size(const vg_plan* plan);
+
+/*
+ * phi = T * f on the N^d grid (Section 4's discrete convolution).
+ * f, phi: device arrays of N^d complex (float2 / double2 per the plan);
+ * phi == f (in place) is allowed.  workspace: device buffer of at least
+ * vg_workspace_size(plan) bytes, 256-byte aligned, or NULL to use the plan's
+ * internal workspace.  Asynchronous on `stream`.
+ * Errors: VG_ERR_INVALID_ARG (NULL plan/pointers), VG_ERR_DEVICE (launch).
+ */
+vg_status vg_apply(const vg_plan* plan, const void* f, void* phi,
+                   void* workspace, void* stream);
+
+/*
+ * Spectral gradient of phi (abstract and Section 3: one extra inverse FFT per
+ * component).  grad: device array of d * N^d complex, component-major
+ * (d/dx_1 first), derivatives with respect to the physical coordinates x_j.
+ * phi may be NULL; when given it receives the same result as vg_apply.
+ * workspace: at least vg_gradient_workspace_size(plan) bytes, or NULL.
+ * The derivative multiplies the (2N)^d spectrum by i pi m_j (m_j the signed
+ * frequency, zero at the Nyquist index m_j = N).
+ */
+vg_status vg_gradient(const vg_plan* plan, const void* f, void* phi, void* grad,
+                      void* workspace, void* stream);
+
+/*
+ * Apply `count` plans to `count` densities in one go: phi[i] = T_i * f[i].
+ * Plans may mix d, N, kernel and k; all must share one precision.  The batch
+ * runs as one persistent kernel launch whose workers take (density, pass,
+ * tile) items in dependency order; the launch is captured in a HIP graph on
+ * first use and replayed while (plans, pointers, workspace, stream) repeat.
+ * workspace: at least vg_batched_workspace_size bytes, or NULL (an internal
+ * buffer owned by the library; such calls must not overlap in time).
+ * Errors: VG_ERR_INVALID_ARG (count <= 0, NULL entries, mixed precision),
+ * VG_ERR_DEVICE.
+ */
+size_t vg_batched_workspace_size(int count, const vg_plan* const* plans);
+vg_status vg_apply_batched(int count, const vg_plan* const* plans,
+                           const void* const* f, void* const* phi,
+                           void* workspace, void* stream);
+
+/*
+ * Copy plan tables to host memory, converted to complex128 (interleaved
+ * doubles).  Synchronous.
+ *   vg_plan_kernel_hat: Khat(m) on the octant m in [0, N]^d, (N+1)^d values,
+ *     C order: the spectrum of T on the (2N)^d box (Khat(m) = Khat(2N - m)
+ *     per axis), as stored for applies (FP32 plans: rounded to float).
+ *   vg_plan_operator_entries: T(n) on n in [0, N)^d, N^d values (T(n) = T(|n|)
+ *     per axis); the entries of the high-order Nystrom matrix (Section 4
+ *     remark).  Needs opts.keep_operator; VG_ERR_INVALID_ARG otherwise.
+ * host_out must hold the stated number of complex128 values.
+ */
+vg_status vg_plan_kernel_hat(const vg_plan* plan, double* host_out);
+vg_status vg_plan_operator_entries(const vg_plan* plan, double* host_out);
+
+/* Human-readable name of a status code (never NULL). */
+const char* vg_status_string(vg_status status);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* vg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VG_H */

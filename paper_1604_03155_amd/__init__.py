@@ -1,0 +1,235 @@
+"""Python binding of the MI355X volume-potential library (libvgconv.so).
+
+Thin ctypes marshalling over the C ABI declared in include/vg.h: every step of
+the computation (kernel precompute, FFT passes, multiplies) runs in the HIP
+library.  PyTorch provides device memory and streams only.  There is no
+fallback: importing this package fails if the library has not been built
+(`python -m paper_1604_03155_amd.build`).
+
+Method: Vico, Greengard, Ferrando, "Fast convolution with free-space Green's
+functions" -- the truncated-kernel FFT convolution phi = g * f on the uniform
+grid x_a = (a - N/2 + 1)/N of [-1/2, 1/2]^d (Section 4), with the kernel's
+truncated Fourier transform from Tables 1 and 2.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "LIBRARY_PATH", "VGError", "Plan", "apply_batched", "batched_workspace_size",
+    "LAPLACE", "HELMHOLTZ", "FP32", "FP64", "status_string",
+]
+
+LIBRARY_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvgconv.so")
+
+LAPLACE, HELMHOLTZ = 0, 1
+FP32, FP64 = 0, 1
+_TUNE = {"off": 0, "quick": 1, "full": 2}
+_KERNELS = {"laplace": LAPLACE, "helmholtz": HELMHOLTZ}
+
+if not os.path.exists(LIBRARY_PATH):
+    raise ImportError(f"{LIBRARY_PATH} is missing: build it with `python -m paper_1604_03155_amd.build`")
+
+_lib = ctypes.CDLL(LIBRARY_PATH)
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("L", ctypes.c_double), ("P", ctypes.c_int),
+                ("tune", ctypes.c_int), ("keep_operator", ctypes.c_int), ("stream", ctypes.c_void_p)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("N", ctypes.c_int), ("kernel", ctypes.c_int), ("precision", ctypes.c_int),
+                ("k", ctypes.c_double), ("L", ctypes.c_double), ("P", ctypes.c_int),
+                ("precompute_ms", ctypes.c_double), ("table_bytes", ctypes.c_size_t),
+                ("workspace_bytes", ctypes.c_size_t), ("gradient_workspace_bytes", ctypes.c_size_t)]
+
+
+_vp = ctypes.c_void_p
+_sig = {
+    "vg_plan_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(_vp)]),
+    "vg_plan_create_ex": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                         ctypes.POINTER(_Opts), ctypes.POINTER(_vp)]),
+    "vg_plan_destroy": (None, [_vp]),
+    "vg_plan_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(_Info)]),
+    "vg_workspace_size": (ctypes.c_size_t, [_vp]),
+    "vg_gradient_workspace_size": (ctypes.c_size_t, [_vp]),
+    "vg_apply": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "vg_gradient": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "vg_batched_workspace_size": (ctypes.c_size_t, [ctypes.c_int, ctypes.POINTER(_vp)]),
+    "vg_apply_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                        ctypes.POINTER(_vp), _vp, _vp]),
+    "vg_plan_kernel_hat": (ctypes.c_int, [_vp, _vp]),
+    "vg_plan_operator_entries": (ctypes.c_int, [_vp, _vp]),
+    "vg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "vg_last_error": (ctypes.c_char_p, []),
+}
+for _name, (_res, _args) in _sig.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+def status_string(code: int) -> str:
+    return _lib.vg_status_string(code).decode()
+
+
+class VGError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = _lib.vg_last_error().decode()
+        super().__init__(f"{where}: {status_string(code)}: {msg}")
+
+
+def _check(code: int, where: str):
+    if code != 0:
+        raise VGError(code, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A precomputed truncated-kernel convolution operator for one grid.
+
+    d: 2 or 3; N: even points per side (h = 1/N); kernel: 'laplace' or
+    'helmholtz' (wavenumber k > 0); precision: 'fp32' (complex64 data, tables
+    built in FP64 and rounded once) or 'fp64'.  L and P default to the paper's
+    truncation radius (1.8 in 3D, 1.5 in 2D) and 4-fold oversampling."""
+
+    def __init__(self, d, N, kernel="laplace", k=0.0, precision="fp32", L=None, P=None, tune="off",
+                 keep_operator=False, stream=None):
+        torch = _torch()
+        self.d, self.N, self.kernel, self.k = int(d), int(N), kernel, float(k)
+        self.precision = precision
+        self._h = None
+        opts = _Opts(FP64 if precision == "fp64" else FP32, float(L or 0.0), int(P or 0), _TUNE[tune],
+                     1 if keep_operator else 0,
+                     stream.cuda_stream if stream is not None else torch.cuda.current_stream().cuda_stream)
+        h = _vp()
+        _check(_lib.vg_plan_create_ex(self.d, self.N, _KERNELS[kernel], self.k, ctypes.byref(opts), ctypes.byref(h)),
+               "vg_plan_create_ex")
+        self._h = h
+        info = _Info()
+        _check(_lib.vg_plan_get_info(h, ctypes.byref(info)), "vg_plan_get_info")
+        self.info = {f: getattr(info, f) for f, _ in _Info._fields_}
+        self.dtype = torch.complex128 if precision == "fp64" else torch.complex64
+
+    # -- housekeeping ------------------------------------------------------
+    def close(self):
+        if self._h:
+            _lib.vg_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def shape(self):
+        return (self.N,) * self.d
+
+    def workspace_size(self, gradient=False):
+        return int((_lib.vg_gradient_workspace_size if gradient else _lib.vg_workspace_size)(self._h))
+
+    def new_workspace(self, gradient=False, device="cuda"):
+        torch = _torch()
+        return torch.empty(max(self.workspace_size(gradient), 1), dtype=torch.uint8, device=device)
+
+    def _check_array(self, a, name, shape=None):
+        torch = _torch()
+        shape = shape or self.shape
+        if not isinstance(a, torch.Tensor) or not a.is_cuda:
+            raise TypeError(f"{name} must be a CUDA tensor")
+        if a.dtype != self.dtype or tuple(a.shape) != tuple(shape) or not a.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {self.dtype} tensor of shape {tuple(shape)}")
+
+    # -- operations ---------------------------------------------------------
+    def apply(self, f, out=None, workspace=None, stream=None):
+        """phi = T * f (Section 4's discrete convolution)."""
+        torch = _torch()
+        self._check_array(f, "f")
+        if out is None:
+            out = torch.empty_like(f)
+        self._check_array(out, "out")
+        ws = _vp(workspace.data_ptr()) if workspace is not None else None
+        _check(_lib.vg_apply(self._h, _vp(f.data_ptr()), _vp(out.data_ptr()), ws, _stream_ptr(stream)), "vg_apply")
+        return out
+
+    def gradient(self, f, with_phi=True, phi=None, grad=None, workspace=None, stream=None):
+        """Returns (phi or None, grad) with grad of shape (d,) + (N,)*d."""
+        torch = _torch()
+        self._check_array(f, "f")
+        if grad is None:
+            grad = torch.empty((self.d,) + self.shape, dtype=self.dtype, device=f.device)
+        self._check_array(grad, "grad", (self.d,) + self.shape)
+        if with_phi and phi is None:
+            phi = torch.empty_like(f)
+        if phi is not None:
+            self._check_array(phi, "phi")
+        ws = _vp(workspace.data_ptr()) if workspace is not None else None
+        _check(_lib.vg_gradient(self._h, _vp(f.data_ptr()), _vp(phi.data_ptr()) if phi is not None else None,
+                                _vp(grad.data_ptr()), ws, _stream_ptr(stream)), "vg_gradient")
+        return phi, grad
+
+    def kernel_hat(self):
+        """Khat on the octant [0, N]^d as complex128 numpy (Section 4)."""
+        import numpy as np
+        out = np.empty((self.N + 1,) * self.d, dtype=np.complex128)
+        _check(_lib.vg_plan_kernel_hat(self._h, _vp(out.ctypes.data)), "vg_plan_kernel_hat")
+        return out
+
+    def operator_entries(self):
+        """T(n) on the octant [0, N)^d as complex128 numpy (needs keep_operator)."""
+        import numpy as np
+        out = np.empty((self.N,) * self.d, dtype=np.complex128)
+        _check(_lib.vg_plan_operator_entries(self._h, _vp(out.ctypes.data)), "vg_plan_operator_entries")
+        return out
+
+
+def _handles(plans):
+    arr = (_vp * len(plans))()
+    for i, p in enumerate(plans):
+        arr[i] = p.handle
+    return arr
+
+
+def batched_workspace_size(plans):
+    return int(_lib.vg_batched_workspace_size(len(plans), _handles(plans)))
+
+
+def apply_batched(plans, fs, outs=None, workspace=None, stream=None):
+    """phi_i = T_i * f_i for a batch of plans of mixed size and kernel."""
+    torch = _torch()
+    if len(plans) != len(fs):
+        raise ValueError("plans and densities differ in length")
+    for p, f in zip(plans, fs):
+        p._check_array(f, "f")
+    if outs is None:
+        outs = [torch.empty_like(f) for f in fs]
+    for p, o in zip(plans, outs):
+        p._check_array(o, "out")
+    n = len(plans)
+    fa = (_vp * n)(*[f.data_ptr() for f in fs])
+    oa = (_vp * n)(*[o.data_ptr() for o in outs])
+    ws = _vp(workspace.data_ptr()) if workspace is not None else None
+    _check(_lib.vg_apply_batched(n, _handles(plans), fa, oa, ws, _stream_ptr(stream)), "vg_apply_batched")
+    return outs

@@ -1,0 +1,115 @@
+// Internal declarations shared by the HIP kernels and the host runtime of the
+// volume-potential library.  Not part of the public ABI (include/vg.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+namespace vg {
+
+// ---------------------------------------------------------------- complex --
+template <typename R>
+struct alignas(2 * sizeof(R)) cplx {
+    R x, y;
+};
+using c32 = cplx<float>;
+using c64 = cplx<double>;
+
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> mk(R a, R b) {
+    cplx<R> c;
+    c.x = a;
+    c.y = b;
+    return c;
+}
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> operator+(cplx<R> a, cplx<R> b) { return mk(a.x + b.x, a.y + b.y); }
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> operator-(cplx<R> a, cplx<R> b) { return mk(a.x - b.x, a.y - b.y); }
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
+    return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> cmulc(cplx<R> a, cplx<R> b) {
+    return mk(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> scale(cplx<R> a, R s) { return mk(a.x * s, a.y * s); }
+
+// ------------------------------------------------------------ FFT passes --
+// A pass runs one batched 1D FFT along one axis of a strided array.  Pencils
+// (1D lines along the axis) are identified by (o, c): outer block o and
+// column c.  Element e of pencil (o, c) lives at  o*so + c + e*se  (element
+// units) for column passes, and at  o*so + e  for row passes (contiguous
+// axis, one column).
+enum PassMode : int { MODE_ROW = 0, MODE_COL = 1 };
+
+// What a pass does between load and store.
+enum PassKind : int {
+    KIND_FWD = 0,        // forward DFT (exponent sign -)
+    KIND_INV = 1,        // inverse DFT (sign +), unnormalised
+    KIND_FUSED = 2,      // forward, multiply by the Khat octant, inverse
+    KIND_FUSED_GRAD = 3, // as FUSED, second output multiplied by i*kappa along this axis
+    KIND_INV_GRAD = 4,   // inverse to out, and inverse of (i*kappa * in) to out2
+};
+
+constexpr int kMaxStages = 12;
+
+struct PassDesc {
+    const void* in;
+    void* out;
+    void* out2;             // second output (gradient kinds)
+    const void* tw;         // twiddles e^{-2 pi i t / L}, t in [0, L)
+    const void* table;      // Khat octant (fused kinds), already divided by (2N)^d
+    long long in_so, out_so;  // outer strides (elements)
+    long long in_se, out_se;  // axis strides (elements)
+    int L;                  // transform length
+    int n_in;               // inputs e >= n_in are zero (pruned zero padding)
+    int n_out;              // only outputs e < n_out are stored (crop)
+    int inner;              // columns per outer block (MODE_COL); 1 for rows
+    int outer;              // outer blocks (MODE_COL) or pencils (MODE_ROW)
+    int C;                  // pencils per workgroup
+    int nst;
+    int radix[kMaxStages];
+    // Khat octant indexing for fused kinds: the pencil's other spectral
+    // indices come from its column: d == 3: c = k2 * (2N) + k3; d == 2: c = k2.
+    int d;
+    int tabN;               // N of the plan (octant is (N+1)^d)
+    int table_complex;      // 0: real table (Laplace), 1: complex
+    // spectral derivative along this pass's axis (gradient kinds): i*kappa,
+    // kappa = kscale * signed(e), zero at the Nyquist index e = L/2.
+    double kscale;
+};
+
+// ----------------------------------------------------- plan precompute ----
+struct GreensParams {
+    int d;
+    int kernel;      // 0 Laplace, 1 Helmholtz
+    double k, L;
+    double ds;       // lattice spacing 2 pi / P
+    // 2D Helmholtz constants H_0^(1)(kL), H_1^(1)(kL) and Taylor
+    // coefficients of the numerator about s = k.
+    double H0r, H0i, H1r, H1i;
+    int ntaylor;
+    double taylor_r[10], taylor_i[10];
+    double window;
+};
+
+// ------------------------------------------------------------- launchers --
+// All return hipSuccess or the first HIP error.
+hipError_t launch_fft_pass(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
+size_t fft_pass_lds_bytes(const PassDesc& p, int kind, bool fp64);
+
+hipError_t launch_greens_contract(const GreensParams& g, int M2, int n_out, const double* cmat,
+                                  c64* out, hipStream_t s);
+hipError_t launch_cos_contract(const c64* in, c64* out, const double* cmat, long long O, int Min,
+                               int Nout, long long I, hipStream_t s);
+hipError_t launch_round_table(const c64* in, void* out, long long n, int to_fp32, int complex_out,
+                              hipStream_t s);
+
+}  // namespace vg

@@ -1,0 +1,463 @@
+// Plan creation: validation, FP64 device precompute of the kernel table
+// (Sections 2 and 4), twiddles, and the pass programs of apply and gradient.
+#include "plan.h"
+
+#include <atomic>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <complex>
+
+namespace vg {
+
+namespace {
+thread_local std::string g_last_error;
+std::atomic<long> g_alloc_count{0};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+}  // namespace
+
+vg_status fail(vg_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+const char* last_error_cstr() { return g_last_error.c_str(); }
+
+vg_status from_hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return VG_OK;
+    if (e == hipErrorOutOfMemory) return fail(VG_ERR_OUT_OF_MEMORY, std::string(what) + ": out of device memory");
+    if (e == hipErrorStreamCaptureUnsupported || e == hipErrorStreamCaptureInvalidated)
+        return fail(VG_ERR_NOT_CAPTURABLE, std::string(what) + ": " + hipGetErrorString(e));
+    return fail(VG_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+hipError_t dev_malloc(void** ptr, size_t bytes) {
+    *ptr = nullptr;
+    const char* hook = std::getenv("VG_TEST_FAIL_ALLOC");
+    const long n = ++g_alloc_count;
+    if (hook && *hook) {
+        const long target = std::atol(hook);
+        if (target > 0 && n == target) return hipErrorOutOfMemory;
+    }
+    if (bytes == 0) bytes = 256;
+    return hipMalloc(ptr, bytes);
+}
+
+std::vector<int> radix_plan(int L) {
+    std::vector<int> r;
+    if (L < 2) return r;
+    int x = L, a = 0;
+    while (x % 2 == 0) {
+        x /= 2;
+        ++a;
+    }
+    std::vector<int> odd;
+    for (int p : {3, 5, 7}) {
+        while (x % p == 0) {
+            x /= p;
+            odd.push_back(p);
+        }
+    }
+    if (x != 1) return {};
+    while (a >= 3) {
+        r.push_back(8);
+        a -= 3;
+    }
+    if (a == 2) r.push_back(4);
+    if (a == 1) r.push_back(2);
+    for (int p : odd) r.push_back(p);
+    return r;
+}
+
+namespace {
+
+// ----------------------------------------------------------- host tables --
+// cos / sin of 2 pi t / n, evaluated in long double from the exact integer
+// ratio and rounded once to the target precision.
+long double twopi_frac_cos(long long t, long long n) {
+    const long double pi = 3.141592653589793238462643383279502884L;
+    return cosl(2.0L * pi * (long double)(t % n) / (long double)n);
+}
+long double twopi_frac_sin(long long t, long long n) {
+    const long double pi = 3.141592653589793238462643383279502884L;
+    return sinl(2.0L * pi * (long double)(t % n) / (long double)n);
+}
+
+// C[n][m] = w_m cos(2 pi n m / period) * scale, n in [0, nout), m in [0, kin)
+std::vector<double> cos_matrix(int nout, int kin, long long period, const std::vector<double>& w, double scale) {
+    std::vector<double> c((size_t)nout * kin);
+    for (int n = 0; n < nout; ++n)
+        for (int m = 0; m < kin; ++m)
+            c[(size_t)n * kin + m] = (double)(twopi_frac_cos((long long)n * m, period) * (long double)w[m] * scale);
+    return c;
+}
+
+double factorial(int n) {
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return f;
+}
+
+double besselj_int(int nu, double x) {
+    if (nu < 0) return ((-nu) % 2 ? -1.0 : 1.0) * std::cyl_bessel_j((double)(-nu), x);
+    return std::cyl_bessel_j((double)nu, x);
+}
+
+// m-th derivative of J_nu: 2^-m sum_j (-1)^j C(m, j) J_{nu-m+2j}
+double besselj_deriv(int nu, int m, double x) {
+    double acc = 0.0, binom = 1.0;
+    for (int j = 0; j <= m; ++j) {
+        acc += ((j % 2) ? -1.0 : 1.0) * binom * besselj_int(nu - m + 2 * j, x);
+        binom = binom * (m - j) / (j + 1);
+    }
+    return std::ldexp(acc, -m);
+}
+
+void fill_greens_params(const vg_plan* p, GreensParams& g) {
+    std::memset(&g, 0, sizeof(g));
+    g.d = p->d;
+    g.kernel = p->kernel;
+    g.k = p->k;
+    g.L = p->L;
+    g.ds = 2.0 * M_PI / p->P;
+    const double L = p->L, k = p->k;
+    if (p->kernel == VG_HELMHOLTZ && p->d == 3) {
+        // power series of (1/s) int_0^L sin(sr) e^{ikr} dr in x^2 = (sL)^2:
+        // a_j = L^2 (-1)^j/(2j+1)! sum_p (ikL)^p / (p! (2j+2+p))
+        g.ntaylor = 10;
+        for (int j = 0; j < 10; ++j) {
+            std::complex<double> inner = 0.0, ikl_p = 1.0;
+            for (int q = 0; q < 40; ++q) {
+                inner += ikl_p / (factorial(q) * (2 * j + 2 + q));
+                ikl_p *= std::complex<double>(0.0, k * L);
+            }
+            const std::complex<double> a = L * L * ((j % 2) ? -1.0 : 1.0) / factorial(2 * j + 1) * inner;
+            g.taylor_r[j] = a.real();
+            g.taylor_i[j] = a.imag();
+        }
+    }
+    if (p->kernel == VG_HELMHOLTZ && p->d == 2) {
+        const double x = k * L;
+        const std::complex<double> H0(std::cyl_bessel_j(0.0, x), std::cyl_neumann(0.0, x));
+        const std::complex<double> H1(std::cyl_bessel_j(1.0, x), std::cyl_neumann(1.0, x));
+        g.H0r = H0.real();
+        g.H0i = H0.imag();
+        g.H1r = H1.real();
+        g.H1i = H1.imag();
+        // Taylor coefficients of N(s)/(s - k) about s = k, N the numerator of
+        // Table 2's transform: c_{n-1} = N^(n)(k)/n!, with
+        // u = s J1(Ls): u^(n) = k L^n J1^(n) + n L^(n-1) J1^(n-1); v = J0(Ls): v^(n) = L^n J0^(n).
+        g.ntaylor = 8;
+        for (int n = 1; n <= 8; ++n) {
+            const double un = k * std::pow(L, n) * besselj_deriv(1, n, x) + n * std::pow(L, n - 1) * besselj_deriv(1, n - 1, x);
+            const double vn = std::pow(L, n) * besselj_deriv(0, n, x);
+            const std::complex<double> Nn = std::complex<double>(0.0, 0.5 * M_PI * L) * (H0 * un - k * H1 * vn);
+            const std::complex<double> c = Nn / factorial(n);
+            g.taylor_r[n - 1] = c.real();
+            g.taylor_i[n - 1] = c.imag();
+        }
+        g.window = 1.0e-2;
+    }
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    hipError_t alloc(size_t bytes) { return dev_malloc(&p, bytes); }
+    template <typename T>
+    T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+vg_status upload(DevBuf& b, const std::vector<double>& h, hipStream_t s) {
+    hipError_t e = b.alloc(h.size() * sizeof(double));
+    if (e != hipSuccess) return from_hip(e, "precompute table allocation");
+    e = hipMemcpyAsync(b.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return from_hip(e, "precompute table upload");
+}
+
+}  // namespace
+
+// FP64 precompute: kernel spectrum -> T (octant) -> Khat (octant) -> table.
+vg_status precompute(vg_plan* p, hipStream_t s, bool keep_T) {
+    const int d = p->d, N = p->N;
+    const long long M = (long long)p->P * N;
+    const int M2 = (int)(M / 2 + 1);
+    std::vector<double> w(M2, 2.0);
+    w[0] = 1.0;
+    w[M2 - 1] = 1.0;
+    const std::vector<double> Cm = cos_matrix(N, M2, M, w, 1.0 / (double)M);
+    std::vector<double> v(N, 2.0);
+    v[0] = 1.0;
+    const std::vector<double> Dm = cos_matrix(N + 1, N, 2LL * N, v, 1.0 / (2.0 * N));
+
+    DevBuf dC, dD;
+    vg_status st = upload(dC, Cm, s);
+    if (st != VG_OK) return st;
+    st = upload(dD, Dm, s);
+    if (st != VG_OK) return st;
+
+    GreensParams g;
+    fill_greens_params(p, g);
+
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    if (he != hipSuccess) return from_hip(he, "hipEventCreate");
+    (void)hipEventRecord(e0, s);
+
+    const long long Nl = N, M2l = M2, N1 = N + 1;
+    DevBuf X1, X2, T, Y1, Y2, K;
+    auto chk = [&](hipError_t e, const char* what) -> vg_status { return from_hip(e, what); };
+    if (d == 3) {
+        if ((he = X1.alloc((size_t)M2l * M2l * Nl * 16)) != hipSuccess) return chk(he, "precompute buffer");
+        if ((he = launch_greens_contract(g, M2, N, dC.as<double>(), X1.as<c64>(), s)) != hipSuccess) return chk(he, "kernel spectrum");
+        if ((he = X2.alloc((size_t)M2l * Nl * Nl * 16)) != hipSuccess) return chk(he, "precompute buffer");
+        if ((he = launch_cos_contract(X1.as<c64>(), X2.as<c64>(), dC.as<double>(), M2l, M2, N, Nl, s)) != hipSuccess) return chk(he, "T axis 2");
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(X1.p);
+        X1.p = nullptr;
+        if ((he = T.alloc((size_t)Nl * Nl * Nl * 16)) != hipSuccess) return chk(he, "precompute buffer");
+        if ((he = launch_cos_contract(X2.as<c64>(), T.as<c64>(), dC.as<double>(), 1, M2, N, Nl * Nl, s)) != hipSuccess) return chk(he, "T axis 1");
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(X2.p);
+        X2.p = nullptr;
+        if ((he = Y1.alloc((size_t)N1 * Nl * Nl * 16)) != hipSuccess) return chk(he, "precompute buffer");
+        if ((he = launch_cos_contract(T.as<c64>(), Y1.as<c64>(), dD.as<double>(), 1, N, N + 1, Nl * Nl, s)) != hipSuccess) return chk(he, "Khat axis 1");
+        if ((he = Y2.alloc((size_t)N1 * N1 * Nl * 16)) != hipSuccess) return chk(he, "precompute buffer");
+        if ((he = launch_cos_contract(Y1.as<c64>(), Y2.as<c64>(), dD.as<double>(), N1, N, N + 1, Nl, s)) != hipSuccess) return chk(he, "Khat axis 2");
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(Y1.p);
+        Y1.p = nullptr;
+        if ((he = K.alloc((size_t)N1 * N1 * N1 * 16)) != hipSuccess) return chk(he, "precompute buffer");
+        if ((he = launch_cos_contract(Y2.as<c64>(), K.as<c64>(), dD.as<double>(), N1 * N1, N, N + 1, 1, s)) != hipSuccess) return chk(he, "Khat axis 3");
+    } else {
+        if ((he = X1.alloc((size_t)M2l * Nl * 16)) != hipSuccess) return chk(he, "precompute buffer");
+        if ((he = launch_greens_contract(g, M2, N, dC.as<double>(), X1.as<c64>(), s)) != hipSuccess) return chk(he, "kernel spectrum");
+        if ((he = T.alloc((size_t)Nl * Nl * 16)) != hipSuccess) return chk(he, "precompute buffer");
+        if ((he = launch_cos_contract(X1.as<c64>(), T.as<c64>(), dC.as<double>(), 1, M2, N, Nl, s)) != hipSuccess) return chk(he, "T axis 1");
+        if ((he = Y1.alloc((size_t)N1 * Nl * 16)) != hipSuccess) return chk(he, "precompute buffer");
+        if ((he = launch_cos_contract(T.as<c64>(), Y1.as<c64>(), dD.as<double>(), 1, N, N + 1, Nl, s)) != hipSuccess) return chk(he, "Khat axis 1");
+        if ((he = K.alloc((size_t)N1 * N1 * 16)) != hipSuccess) return chk(he, "precompute buffer");
+        if ((he = launch_cos_contract(Y1.as<c64>(), K.as<c64>(), dD.as<double>(), N1, N, N + 1, 1, s)) != hipSuccess) return chk(he, "Khat axis 2");
+    }
+    long long nK = 1;
+    for (int i = 0; i < d; ++i) nK *= N1;
+    p->table_complex = (p->kernel == VG_HELMHOLTZ) ? 1 : 0;
+    const size_t esz = (p->fp64 ? 8 : 4) * (p->table_complex ? 2 : 1);
+    p->table_bytes = (size_t)nK * esz;
+    if ((he = dev_malloc(&p->table, p->table_bytes)) != hipSuccess) return chk(he, "kernel table");
+    if ((he = launch_round_table(K.as<c64>(), p->table, nK, p->fp64 ? 0 : 1, p->table_complex, s)) != hipSuccess)
+        return chk(he, "table rounding");
+    (void)hipEventRecord(e1, s);
+    if ((he = hipStreamSynchronize(s)) != hipSuccess) return chk(he, "precompute");
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    p->precompute_ms = ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (keep_T) {
+        p->T_dev = T.p;  // ownership moves to the plan
+        T.p = nullptr;
+    }
+    return VG_OK;
+}
+
+vg_status make_twiddles(vg_plan* p, hipStream_t s) {
+    const int L = 2 * p->N;
+    const size_t esz = p->fp64 ? 16 : 8;
+    std::vector<unsigned char> h((size_t)L * esz);
+    for (int t = 0; t < L; ++t) {
+        const long double c = twopi_frac_cos(t, L), sn = -twopi_frac_sin(t, L);
+        if (p->fp64) {
+            double* q = reinterpret_cast<double*>(h.data()) + 2 * t;
+            q[0] = (double)c;
+            q[1] = (double)sn;
+        } else {
+            float* q = reinterpret_cast<float*>(h.data()) + 2 * t;
+            q[0] = (float)c;
+            q[1] = (float)sn;
+        }
+    }
+    hipError_t e = dev_malloc(&p->twiddle, h.size());
+    if (e != hipSuccess) return from_hip(e, "twiddle allocation");
+    e = hipMemcpyAsync(p->twiddle, h.data(), h.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return from_hip(e, "twiddle upload");
+}
+
+// ------------------------------------------------------------- programs --
+namespace {
+
+PassDesc base_desc(const vg_plan* p) {
+    PassDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.L = 2 * p->N;
+    d.nst = (int)p->radices.size();
+    for (int i = 0; i < d.nst; ++i) d.radix[i] = p->radices[i];
+    d.tw = p->twiddle;
+    d.table = p->table;
+    d.d = p->d;
+    d.tabN = p->N;
+    d.table_complex = p->table_complex;
+    d.kscale = M_PI;  // the 2N box has period 2 in x: kappa = pi * m
+    return d;
+}
+
+PassStep row_step(const vg_plan* p, int kind, int in_buf, long long in_pitch, int n_in, int out_buf,
+                  long long out_pitch, int n_out, long long rows, const char* name, int out2_buf = BUF_NONE) {
+    PassStep s;
+    s.desc = base_desc(p);
+    s.desc.in_so = in_pitch;
+    s.desc.in_se = 1;
+    s.desc.out_so = out_pitch;
+    s.desc.out_se = 1;
+    s.desc.n_in = n_in;
+    s.desc.n_out = n_out;
+    s.desc.inner = 1;
+    s.desc.outer = (int)rows;
+    s.desc.C = p->tc.C_row;
+    s.mode = MODE_ROW;
+    s.kind = kind;
+    s.in_buf = in_buf;
+    s.out_buf = out_buf;
+    s.out2_buf = out2_buf;
+    s.name = name;
+    return s;
+}
+
+PassStep col_step(const vg_plan* p, int kind, int in_buf, long long in_so, long long in_se, int n_in, int out_buf,
+                  long long out_so, long long out_se, int n_out, long long inner, long long outer, const char* name,
+                  int out2_buf = BUF_NONE) {
+    PassStep s;
+    s.desc = base_desc(p);
+    s.desc.in_so = in_so;
+    s.desc.in_se = in_se;
+    s.desc.out_so = out_so;
+    s.desc.out_se = out_se;
+    s.desc.n_in = n_in;
+    s.desc.n_out = n_out;
+    s.desc.inner = (int)inner;
+    s.desc.outer = (int)outer;
+    s.desc.C = (kind == KIND_FUSED || kind == KIND_FUSED_GRAD) ? p->tc.C_fused : p->tc.C_col;
+    s.mode = MODE_COL;
+    s.kind = kind;
+    s.in_buf = in_buf;
+    s.out_buf = out_buf;
+    s.out2_buf = out2_buf;
+    s.name = name;
+    return s;
+}
+
+void set_ws(Program& prog, const std::vector<size_t>& sizes_bytes) {
+    prog.ws_offsets.clear();
+    size_t off = 0;
+    for (size_t b : sizes_bytes) {
+        prog.ws_offsets.push_back(off);
+        off += align256(b);
+    }
+    prog.ws_bytes = off;
+}
+
+}  // namespace
+
+void build_programs(vg_plan* p) {
+    const long long N = p->N, L = 2 * N;
+    const size_t es = p->fp64 ? 16 : 8;
+    const int W0 = BUF_WS0, W1 = BUF_WS0 + 1, W2 = BUF_WS0 + 2, W3 = BUF_WS0 + 3, W4 = BUF_WS0 + 4;
+    Program& A = p->apply_prog;
+    Program& G = p->grad_prog;
+    A.steps.clear();
+    G.steps.clear();
+    if (p->d == 3) {
+        const long long V = N * N * N;
+        // apply: f -(rows, axis 3)-> W0[N][N][L] -(axis 2)-> W1[N][L][L]
+        //        -(axis 1: fwd, Khat, inv, crop; in place)-> W1
+        //        -(axis 2 inverse, crop)-> W0[N][N][L] -(rows inverse, crop)-> phi
+        set_ws(A, {(size_t)(2 * V) * es, (size_t)(4 * V) * es});
+        A.steps.push_back(row_step(p, KIND_FWD, BUF_F, N, (int)N, W0, L, (int)L, N * N, "p1_row_fwd"));
+        A.steps.push_back(col_step(p, KIND_FWD, W0, N * L, L, (int)N, W1, L * L, L, (int)L, L, N, "p2_col_fwd"));
+        A.steps.push_back(col_step(p, KIND_FUSED, W1, 0, L * L, (int)N, W1, 0, L * L, (int)N, L * L, 1, "p3_fused"));
+        A.steps.push_back(col_step(p, KIND_INV, W1, L * L, L, (int)L, W0, N * L, L, (int)N, L, N, "p4_col_inv"));
+        A.steps.push_back(row_step(p, KIND_INV, W0, L, (int)L, BUF_PHI, N, (int)N, N * N, "p5_row_inv"));
+        // gradient: W0 (2V), W1 (4V), W2 (4V), W3 (2V), W4 (2V)
+        set_ws(G, {(size_t)(2 * V) * es, (size_t)(4 * V) * es, (size_t)(4 * V) * es, (size_t)(2 * V) * es,
+                   (size_t)(2 * V) * es});
+        G.steps.push_back(row_step(p, KIND_FWD, BUF_F, N, (int)N, W0, L, (int)L, N * N, "g1_row_fwd"));
+        G.steps.push_back(col_step(p, KIND_FWD, W0, N * L, L, (int)N, W1, L * L, L, (int)L, L, N, "g2_col_fwd"));
+        G.steps.push_back(col_step(p, KIND_FUSED_GRAD, W1, 0, L * L, (int)N, W1, 0, L * L, (int)N, L * L, 1,
+                                   "g3_fused_grad", W2));
+        G.steps.push_back(col_step(p, KIND_INV_GRAD, W1, L * L, L, (int)L, W0, N * L, L, (int)N, L, N,
+                                   "g4_col_inv_grad", W3));
+        G.steps.push_back(col_step(p, KIND_INV, W2, L * L, L, (int)L, W4, N * L, L, (int)N, L, N, "g4_col_inv"));
+        G.steps.push_back(row_step(p, KIND_INV_GRAD, W0, L, (int)L, BUF_PHI, N, (int)N, N * N, "g5_row_inv_grad",
+                                   BUF_GRAD0 + 2));
+        G.steps.push_back(row_step(p, KIND_INV, W3, L, (int)L, BUF_GRAD0 + 1, N, (int)N, N * N, "g5_row_inv_d2"));
+        G.steps.push_back(row_step(p, KIND_INV, W4, L, (int)L, BUF_GRAD0 + 0, N, (int)N, N * N, "g5_row_inv_d1"));
+    } else {
+        const long long V = N * N;
+        set_ws(A, {(size_t)(2 * V) * es});
+        A.steps.push_back(row_step(p, KIND_FWD, BUF_F, N, (int)N, W0, L, (int)L, N, "p1_row_fwd"));
+        A.steps.push_back(col_step(p, KIND_FUSED, W0, 0, L, (int)N, W0, 0, L, (int)N, L, 1, "p2_fused"));
+        A.steps.push_back(row_step(p, KIND_INV, W0, L, (int)L, BUF_PHI, N, (int)N, N, "p3_row_inv"));
+        set_ws(G, {(size_t)(2 * V) * es, (size_t)(2 * V) * es});
+        G.steps.push_back(row_step(p, KIND_FWD, BUF_F, N, (int)N, W0, L, (int)L, N, "g1_row_fwd"));
+        G.steps.push_back(col_step(p, KIND_FUSED_GRAD, W0, 0, L, (int)N, W0, 0, L, (int)N, L, 1, "g2_fused_grad", W1));
+        G.steps.push_back(row_step(p, KIND_INV_GRAD, W0, L, (int)L, BUF_PHI, N, (int)N, N, "g3_row_inv_grad",
+                                   BUF_GRAD0 + 1));
+        G.steps.push_back(row_step(p, KIND_INV, W1, L, (int)L, BUF_GRAD0 + 0, N, (int)N, N, "g3_row_inv_d1"));
+    }
+}
+
+vg_status run_program(const vg_plan* p, const Program& prog, const void* f, void* phi, void* grad, void* ws,
+                      hipStream_t stream) {
+    const long long N = p->N;
+    long long V = 1;
+    for (int i = 0; i < p->d; ++i) V *= N;
+    const size_t es = p->fp64 ? 16 : 8;
+    auto resolve = [&](int id) -> void* {
+        if (id == BUF_F) return const_cast<void*>(f);
+        if (id == BUF_PHI) return phi;
+        if (id >= BUF_GRAD0 && id < BUF_GRAD0 + 3)
+            return grad ? static_cast<unsigned char*>(grad) + (size_t)(id - BUF_GRAD0) * V * es : nullptr;
+        if (id >= BUF_WS0 && id < BUF_WS0 + 8) return static_cast<unsigned char*>(ws) + prog.ws_offsets[id - BUF_WS0];
+        return nullptr;
+    };
+    for (const PassStep& st : prog.steps) {
+        PassDesc d = st.desc;
+        d.in = resolve(st.in_buf);
+        d.out = resolve(st.out_buf);
+        d.out2 = resolve(st.out2_buf);
+        int kind = st.kind;
+        if (kind == KIND_INV_GRAD && d.out == nullptr) {
+            // gradient without phi: derivative-only inverse into out2
+            d.out = d.out2;
+            d.out2 = nullptr;
+            kind = 100 + KIND_INV;
+        }
+        hipError_t e = launch_fft_pass(d, st.mode, kind, p->fp64, stream);
+        if (e != hipSuccess) return from_hip(e, st.name);
+    }
+    return VG_OK;
+}
+
+vg_status autotune(vg_plan* p) {
+    // Built-in shapes: pencils per workgroup sized so the ping-pong LDS stays
+    // within 64 KiB where possible.
+    const int L = 2 * p->N;
+    const size_t es = p->fp64 ? 16 : 8;
+    auto pick = [&](int nbuf, int cmax) {
+        int c = cmax;
+        while (c > 1 && (size_t)nbuf * c * L * es > 65536) c /= 2;
+        return c;
+    };
+    p->tc.C_col = pick(3, 16);
+    p->tc.C_fused = pick(3, 16);
+    p->tc.C_row = pick(3, 4);
+    return VG_OK;
+}
+
+}  // namespace vg

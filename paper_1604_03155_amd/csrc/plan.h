@@ -1,0 +1,88 @@
+// Host-side plan object of the volume-potential library (internal).
+#pragma once
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "../../include/vg.h"
+
+namespace vg {
+
+// One launch of a pass: descriptor plus how to launch it.  Buffer fields of
+// the descriptor are filled in at apply time from symbolic buffer ids.
+enum BufId : int {
+    BUF_F = 0,     // caller's density
+    BUF_PHI = 1,   // caller's potential (may be null for gradient-only)
+    BUF_GRAD0 = 2, // caller's gradient component 0 (then 1, 2)
+    BUF_WS0 = 8,   // workspace sub-buffers 0..7
+    BUF_NONE = 63
+};
+
+struct PassStep {
+    PassDesc desc;   // in/out/out2 filled at apply time
+    int mode;        // MODE_ROW / MODE_COL
+    int kind;        // PassKind (or 100 + KIND_INV for derivative-only inverse)
+    int in_buf, out_buf, out2_buf;
+    const char* name;
+};
+
+struct Program {
+    std::vector<PassStep> steps;
+    std::vector<size_t> ws_offsets;  // byte offsets of workspace sub-buffers
+    size_t ws_bytes = 0;
+};
+
+// Launch shape chosen for each pass role (pencils per workgroup).
+struct TuneChoice {
+    int C_row = 0, C_col = 0, C_fused = 0;
+};
+
+}  // namespace vg
+
+struct vg_plan {
+    int d = 0, N = 0, kernel = 0, precision = 0, P = 4, tune = 0;
+    double k = 0.0, L = 0.0;
+    int device = 0;
+    bool fp64 = false;
+    std::vector<int> radices;     // Stockham radix plan of length 2N
+    void* twiddle = nullptr;      // device, 2N complex (float or double)
+    void* table = nullptr;        // device, (N+1)^d Khat octant / (2N)^d
+    size_t table_bytes = 0;
+    int table_complex = 0;
+    void* T_dev = nullptr;        // device, N^d complex128 (keep_operator)
+    double precompute_ms = 0.0;
+    vg::TuneChoice tc;
+    vg::Program apply_prog, grad_prog;
+    // internal workspace for calls with workspace == NULL
+    mutable std::mutex ws_mutex;
+    mutable void* internal_ws = nullptr;
+    mutable size_t internal_ws_bytes = 0;
+};
+
+namespace vg {
+
+// Set the calling thread's error message; returns `st`.
+vg_status fail(vg_status st, const std::string& msg);
+vg_status from_hip(hipError_t e, const char* what);
+
+// Radix plan for length L with radices in {8, 4, 2, 3, 5, 7}; empty if L has
+// another prime factor.
+std::vector<int> radix_plan(int L);
+
+// Build the apply / gradient programs for a plan (after tuning choices).
+void build_programs(vg_plan* p);
+
+// Run a program: bind buffers and launch every step on `stream`.
+vg_status run_program(const vg_plan* p, const Program& prog, const void* f, void* phi, void* grad,
+                      void* ws, hipStream_t stream);
+
+// Plan-time autotuning of pencils per workgroup.
+vg_status autotune(vg_plan* p);
+
+// Device allocation with the test hook VG_TEST_FAIL_ALLOC=n (the n-th
+// allocation made through this function fails).
+hipError_t dev_malloc(void** ptr, size_t bytes);
+
+}  // namespace vg

@@ -1,0 +1,174 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle.
+
+Bars: FP64 plans match the oracle to 1e-12 (relative L2 over all outputs, and
+relative to the table's largest entry for plan tables); FP32 plans to 1e-5
+relative L2 (the stated target for complex64 bulk arithmetic with tables built
+in FP64 and rounded once).  Sizes span several workgroup tiles, ragged tile
+tails, every radix (2, 3, 4, 5, 7, 8) and the smallest grid.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+def _vg():
+    import paper_1604_03155_amd as vg
+    return vg
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def random_density(seed, d, N):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal((N,) * d) + 1j * rng.standard_normal((N,) * d)).astype(np.complex128)
+
+
+def to_dev(f, precision):
+    torch = _torch()
+    dt = torch.complex128 if precision == "fp64" else torch.complex64
+    return torch.from_numpy(f).to(dtype=dt, device="cuda").contiguous()
+
+
+def oracle_plan(d, N, kernel, k):
+    from oracle import operator as op
+    return op.Plan(d, N, kernel, k)
+
+
+TABLE_CASES = [
+    (3, 4, "laplace", 0.0), (3, 8, "laplace", 0.0), (3, 8, "helmholtz", 20.0), (3, 12, "helmholtz", 0.4),
+    (3, 10, "helmholtz", 7.5), (2, 16, "laplace", 0.0), (2, 16, "helmholtz", 30.0), (2, 20, "helmholtz", 2.0),
+    (2, 30, "helmholtz", 200.0), (2, 6, "laplace", 0.0),
+]
+
+
+@pytest.mark.parametrize("d,N,kernel,k", TABLE_CASES)
+def test_plan_tables_fp64_match_oracle(d, N, kernel, k):
+    say("tables", d, N, kernel, k)
+    vg = _vg()
+    p = vg.Plan(d, N, kernel, k, precision="fp64", keep_operator=True)
+    o = oracle_plan(d, N, kernel, k)
+    T = p.operator_entries()
+    K = p.kernel_hat()
+    assert np.max(np.abs(T - o.T_oct)) <= FP64_TOL * np.max(np.abs(o.T_oct))
+    assert np.max(np.abs(K - o.K_oct)) <= FP64_TOL * np.max(np.abs(o.K_oct))
+
+
+@pytest.mark.parametrize("d,N,kernel,k", [(3, 8, "helmholtz", 20.0), (2, 16, "laplace", 0.0)])
+def test_plan_table_fp32_rounded_once(d, N, kernel, k):
+    vg = _vg()
+    p = vg.Plan(d, N, kernel, k, precision="fp32")
+    o = oracle_plan(d, N, kernel, k)
+    K = p.kernel_hat()
+    # each stored entry is the FP64 value rounded to float (relative 2^-24 per part)
+    err = np.abs(K - o.K_oct)
+    assert np.max(err) <= 1.2e-7 * np.max(np.abs(o.K_oct))
+
+
+APPLY_CASES = [
+    (3, 4, "laplace", 0.0), (3, 6, "helmholtz", 3.0), (3, 8, "helmholtz", 20.0), (3, 10, "laplace", 0.0),
+    (3, 14, "helmholtz", 5.0), (3, 16, "laplace", 0.0), (3, 24, "helmholtz", 11.0), (3, 30, "helmholtz", 9.0),
+    (3, 32, "laplace", 0.0),
+    (2, 4, "laplace", 0.0), (2, 6, "helmholtz", 3.0), (2, 10, "laplace", 0.0), (2, 14, "helmholtz", 40.0),
+    (2, 30, "laplace", 0.0), (2, 64, "helmholtz", 60.0), (2, 100, "laplace", 0.0), (2, 256, "helmholtz", 100.0),
+]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("d,N,kernel,k", APPLY_CASES)
+def test_apply_matches_oracle(d, N, kernel, k, precision):
+    say("apply", d, N, kernel, k, precision)
+    vg = _vg()
+    torch = _torch()
+    f = random_density(100 + N, d, N)
+    p = vg.Plan(d, N, kernel, k, precision=precision)
+    phi = p.apply(to_dev(f, precision))
+    torch.cuda.synchronize()
+    ref = oracle_plan(d, N, kernel, k).apply(f)
+    err = rel_l2(phi.cpu().numpy(), ref)
+    assert err <= (FP64_TOL if precision == "fp64" else FP32_TOL), err
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("d,N,kernel,k", [(3, 8, "helmholtz", 6.0), (3, 12, "laplace", 0.0),
+                                          (3, 20, "helmholtz", 13.0), (2, 16, "helmholtz", 25.0),
+                                          (2, 30, "laplace", 0.0), (2, 64, "helmholtz", 7.0)])
+def test_gradient_matches_oracle(d, N, kernel, k, precision):
+    say("gradient", d, N, kernel, k, precision)
+    vg = _vg()
+    torch = _torch()
+    f = random_density(200 + N, d, N)
+    p = vg.Plan(d, N, kernel, k, precision=precision)
+    phi, grad = p.gradient(to_dev(f, precision))
+    _, grad_only = p.gradient(to_dev(f, precision), with_phi=False)
+    torch.cuda.synchronize()
+    o = oracle_plan(d, N, kernel, k)
+    tol = FP64_TOL if precision == "fp64" else FP32_TOL
+    assert rel_l2(phi.cpu().numpy(), o.apply(f)) <= tol
+    gref = o.gradient(f)
+    for j in range(d):
+        assert rel_l2(grad[j].cpu().numpy(), gref[j]) <= tol, j
+    assert torch.equal(grad, grad_only)
+
+
+def test_in_place_and_zero_density():
+    vg = _vg()
+    torch = _torch()
+    N = 16
+    f = random_density(5, 3, N)
+    p = vg.Plan(3, N, "helmholtz", 9.0, precision="fp64")
+    x = to_dev(f, "fp64")
+    ref = p.apply(x).clone()
+    p.apply(x, out=x)
+    torch.cuda.synchronize()
+    assert torch.equal(x, ref)
+    z = torch.zeros((N,) * 3, dtype=torch.complex128, device="cuda")
+    assert torch.count_nonzero(p.apply(z)).item() == 0
+
+
+def test_explicit_workspace_and_stream():
+    vg = _vg()
+    torch = _torch()
+    N = 24
+    f = random_density(6, 3, N)
+    p = vg.Plan(3, N, "laplace", precision="fp32")
+    ws = p.new_workspace()
+    s = torch.cuda.Stream()
+    x = to_dev(f, "fp32")
+    ref = p.apply(x)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        out = p.apply(x, workspace=ws, stream=s)
+    s.synchronize()
+    assert torch.equal(out, ref)
+
+
+def test_linearity_on_gpu():
+    vg = _vg()
+    torch = _torch()
+    N = 16
+    p = vg.Plan(3, N, "helmholtz", 4.0, precision="fp64")
+    a = to_dev(random_density(7, 3, N), "fp64")
+    b = to_dev(random_density(8, 3, N), "fp64")
+    c1, c2 = 0.7 - 0.2j, -1.3
+    lhs = p.apply(c1 * a + c2 * b)
+    rhs = c1 * p.apply(a) + c2 * p.apply(b)
+    assert (torch.linalg.vector_norm(lhs - rhs) / torch.linalg.vector_norm(rhs)).item() < 1e-13
