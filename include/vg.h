@@ -178,6 +178,29 @@ vg_status vg_apply_batched(int count, const vg_plan* const* plans,
 vg_status vg_plan_kernel_hat(const vg_plan* plan, double* host_out);
 vg_status vg_plan_operator_entries(const vg_plan* plan, double* host_out);
 
+/*
+ * Pass profiler (diagnostics).  While enabled, every apply / gradient call
+ * records a HIP event between consecutive passes on its stream; collect()
+ * waits for those events and returns, per pass name, the number of launches
+ * and their summed device time, then clears the record.  Enabling adds one
+ * event record per pass to the stream.  Process-wide; thread-safe.
+ */
+typedef struct vg_pass_time {
+    char name[32];
+    int launches;
+    double total_ms;
+    double bytes_per_launch;  /* algorithmic HBM bytes of one launch (reads + writes) */
+} vg_pass_time;
+vg_status vg_profiler_enable(int enable);
+vg_status vg_profiler_collect(vg_pass_time* out, int max_entries, int* n_entries);
+
+/*
+ * Plain streaming copy of `bytes` bytes (multiple of 16) between device
+ * buffers on `stream`: the reference kernel for attainable HBM bandwidth and
+ * for calibrating hardware byte counters.  Errors: VG_ERR_INVALID_ARG.
+ */
+vg_status vg_hbm_copy(void* dst, const void* src, size_t bytes, void* stream);
+
 /* Human-readable name of a status code (never NULL). */
 const char* vg_status_string(vg_status status);
 

@@ -35,7 +35,11 @@ P_DEFAULT = 4
 
 
 def _workers():
+    """Threads for the library FFT: OMP_NUM_THREADS when set, else all cores."""
     import os
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
     return max(1, os.cpu_count() or 1)
 
 

@@ -18,7 +18,7 @@ import os
 
 __all__ = [
     "LIBRARY_PATH", "VGError", "Plan", "apply_batched", "batched_workspace_size",
-    "LAPLACE", "HELMHOLTZ", "FP32", "FP64", "status_string",
+    "LAPLACE", "HELMHOLTZ", "FP32", "FP64", "status_string", "profiler_enable", "profiler_collect", "hbm_copy",
 ]
 
 LIBRARY_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvgconv.so")
@@ -46,6 +46,11 @@ class _Info(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_size_t), ("gradient_workspace_bytes", ctypes.c_size_t)]
 
 
+class _PassTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int), ("total_ms", ctypes.c_double),
+                ("bytes_per_launch", ctypes.c_double)]
+
+
 _vp = ctypes.c_void_p
 _sig = {
     "vg_plan_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(_vp)]),
@@ -62,6 +67,9 @@ _sig = {
                                         ctypes.POINTER(_vp), _vp, _vp]),
     "vg_plan_kernel_hat": (ctypes.c_int, [_vp, _vp]),
     "vg_plan_operator_entries": (ctypes.c_int, [_vp, _vp]),
+    "vg_profiler_enable": (ctypes.c_int, [ctypes.c_int]),
+    "vg_profiler_collect": (ctypes.c_int, [ctypes.POINTER(_PassTime), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "vg_hbm_copy": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp]),
     "vg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "vg_last_error": (ctypes.c_char_p, []),
 }
@@ -203,6 +211,28 @@ class Plan:
         out = np.empty((self.N,) * self.d, dtype=np.complex128)
         _check(_lib.vg_plan_operator_entries(self._h, _vp(out.ctypes.data)), "vg_plan_operator_entries")
         return out
+
+
+def profiler_enable(enable=True):
+    """Record device time per pass of every apply / gradient call."""
+    _check(_lib.vg_profiler_enable(1 if enable else 0), "vg_profiler_enable")
+
+
+def profiler_collect():
+    """Wait for recorded passes; return [{name, launches, total_ms, bytes_per_launch}] and clear."""
+    buf = (_PassTime * 64)()
+    n = ctypes.c_int(0)
+    _check(_lib.vg_profiler_collect(buf, 64, ctypes.byref(n)), "vg_profiler_collect")
+    return [dict(name=buf[i].name.decode(), launches=buf[i].launches, total_ms=buf[i].total_ms,
+                 bytes_per_launch=buf[i].bytes_per_launch) for i in range(n.value)]
+
+
+def hbm_copy(dst, src, stream=None):
+    """Streaming copy between two CUDA tensors of equal byte size."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("size mismatch")
+    _check(_lib.vg_hbm_copy(_vp(dst.data_ptr()), _vp(src.data_ptr()), nbytes, _stream_ptr(stream)), "vg_hbm_copy")
 
 
 def _handles(plans):

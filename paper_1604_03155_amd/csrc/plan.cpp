@@ -86,10 +86,12 @@ long double twopi_frac_sin(long long t, long long n) {
 
 // C[n][m] = w_m cos(2 pi n m / period) * scale, n in [0, nout), m in [0, kin)
 std::vector<double> cos_matrix(int nout, int kin, long long period, const std::vector<double>& w, double scale) {
+    std::vector<long double> ct((size_t)period);
+    for (long long t = 0; t < period; ++t) ct[(size_t)t] = twopi_frac_cos(t, period);
     std::vector<double> c((size_t)nout * kin);
     for (int n = 0; n < nout; ++n)
         for (int m = 0; m < kin; ++m)
-            c[(size_t)n * kin + m] = (double)(twopi_frac_cos((long long)n * m, period) * (long double)w[m] * scale);
+            c[(size_t)n * kin + m] = (double)(ct[(size_t)(((long long)n * m) % period)] * (long double)w[m] * scale);
     return c;
 }
 
@@ -364,6 +366,8 @@ void set_ws(Program& prog, const std::vector<size_t>& sizes_bytes) {
 
 }  // namespace
 
+void finalize_bytes(vg_plan* p);
+
 void build_programs(vg_plan* p) {
     const long long N = p->N, L = 2 * N;
     const size_t es = p->fp64 ? 16 : 8;
@@ -410,6 +414,26 @@ void build_programs(vg_plan* p) {
                                    BUF_GRAD0 + 1));
         G.steps.push_back(row_step(p, KIND_INV, W1, L, (int)L, BUF_GRAD0 + 0, N, (int)N, N, "g3_row_inv_d1"));
     }
+    finalize_bytes(p);
+}
+
+namespace {
+// Algorithmic bytes of a pass: each pencil reads its n_in nonzero inputs and
+// writes its n_out kept outputs (twice for two-output kinds); fused passes
+// also read the Khat octant once.
+double pass_bytes(const vg_plan* p, const PassStep& s) {
+    const double es = p->fp64 ? 16.0 : 8.0;
+    const double pencils = (s.mode == MODE_COL) ? (double)s.desc.outer * s.desc.inner : (double)s.desc.outer;
+    double outs = (s.out2_buf != BUF_NONE) ? 2.0 : 1.0;
+    double b = pencils * es * (s.desc.n_in + outs * s.desc.n_out);
+    if (s.kind == KIND_FUSED || s.kind == KIND_FUSED_GRAD) b += (double)p->table_bytes;
+    return b;
+}
+}  // namespace
+
+void finalize_bytes(vg_plan* p) {
+    for (Program* pr : {&p->apply_prog, &p->grad_prog})
+        for (PassStep& s : pr->steps) s.bytes = pass_bytes(p, s);
 }
 
 vg_status run_program(const vg_plan* p, const Program& prog, const void* f, void* phi, void* grad, void* ws,
@@ -426,6 +450,7 @@ vg_status run_program(const vg_plan* p, const Program& prog, const void* f, void
         if (id >= BUF_WS0 && id < BUF_WS0 + 8) return static_cast<unsigned char*>(ws) + prog.ws_offsets[id - BUF_WS0];
         return nullptr;
     };
+    void* mark = profiler_mark(stream);
     for (const PassStep& st : prog.steps) {
         PassDesc d = st.desc;
         d.in = resolve(st.in_buf);
@@ -440,6 +465,11 @@ vg_status run_program(const vg_plan* p, const Program& prog, const void* f, void
         }
         hipError_t e = launch_fft_pass(d, st.mode, kind, p->fp64, stream);
         if (e != hipSuccess) return from_hip(e, st.name);
+        if (mark) {
+            void* next = profiler_mark(stream);
+            profiler_add(st.name, mark, next, st.bytes);
+            mark = next;
+        }
     }
     return VG_OK;
 }

@@ -26,6 +26,7 @@ struct PassStep {
     int kind;        // PassKind (or 100 + KIND_INV for derivative-only inverse)
     int in_buf, out_buf, out2_buf;
     const char* name;
+    double bytes;    // algorithmic HBM bytes of one launch (reads + writes)
 };
 
 struct Program {
@@ -80,6 +81,11 @@ vg_status run_program(const vg_plan* p, const Program& prog, const void* f, void
 
 // Plan-time autotuning of pencils per workgroup.
 vg_status autotune(vg_plan* p);
+
+// Pass profiler hooks (profiler.cpp).
+bool profiler_enabled();
+void* profiler_mark(hipStream_t s);
+void profiler_add(const char* name, void* a, void* b, double bytes);
 
 // Device allocation with the test hook VG_TEST_FAIL_ALLOC=n (the n-th
 // allocation made through this function fails).
