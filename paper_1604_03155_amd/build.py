@@ -23,7 +23,7 @@ LIB = os.path.join(PKG, "libvgconv.so")
 ARCH = "gfx950"
 
 CFLAGS = [
-    "-x", "hip", "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
+    "-x", "hip", "-std=c++20", "-O3", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     "-I", os.path.join(ROOT, "include"),

@@ -1,0 +1,50 @@
+// Dispatch of the length-specialised FFT passes (kernels in fft_fast_impl.h,
+// one translation unit per length).
+#include "common.h"
+
+namespace vg {
+
+int fast_C_64(int mode, bool fp64);
+hipError_t launch_fast_64(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
+int fast_C_96(int mode, bool fp64);
+hipError_t launch_fast_96(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
+int fast_C_128(int mode, bool fp64);
+hipError_t launch_fast_128(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
+int fast_C_192(int mode, bool fp64);
+hipError_t launch_fast_192(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
+int fast_C_256(int mode, bool fp64);
+hipError_t launch_fast_256(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
+int fast_C_512(int mode, bool fp64);
+hipError_t launch_fast_512(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
+int fast_C_1024(int mode, bool fp64);
+hipError_t launch_fast_1024(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
+
+// Pencils per workgroup the specialised kernel uses for (L, mode, precision),
+// or 0 when no specialisation exists (the generic kernel is used).
+int fast_pass_C(int L, int mode, bool fp64) {
+    switch (L) {
+        case 64: return fast_C_64(mode, fp64);
+        case 96: return fast_C_96(mode, fp64);
+        case 128: return fast_C_128(mode, fp64);
+        case 192: return fast_C_192(mode, fp64);
+        case 256: return fast_C_256(mode, fp64);
+        case 512: return fast_C_512(mode, fp64);
+        case 1024: return fast_C_1024(mode, fp64);
+        default: return 0;
+    }
+}
+
+hipError_t launch_fast_pass(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s) {
+    switch (p.L) {
+        case 64: return launch_fast_64(p, mode, kind, fp64, s);
+        case 96: return launch_fast_96(p, mode, kind, fp64, s);
+        case 128: return launch_fast_128(p, mode, kind, fp64, s);
+        case 192: return launch_fast_192(p, mode, kind, fp64, s);
+        case 256: return launch_fast_256(p, mode, kind, fp64, s);
+        case 512: return launch_fast_512(p, mode, kind, fp64, s);
+        case 1024: return launch_fast_1024(p, mode, kind, fp64, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace vg

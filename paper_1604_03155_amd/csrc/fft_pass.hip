@@ -283,8 +283,14 @@ size_t fft_pass_lds_bytes(const PassDesc& p, int kind, bool fp64) {
     return (size_t)lds_buffers(kind) * p.C * p.L * (fp64 ? 16 : 8);
 }
 
-// kind values >= 100 select the derivative-only inverse (kind - 100 ignored)
+int fast_pass_C(int L, int mode, bool fp64);
+hipError_t launch_fast_pass(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
+
+// kind values >= 100 select the derivative-only inverse (kind - 100 ignored).
+// Lengths with a specialised kernel go there when the descriptor's tile width
+// matches its shape; everything else runs the generic kernel.
 hipError_t launch_fft_pass(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s) {
+    if (p.C > 0 && fast_pass_C(p.L, mode, fp64) == p.C) return launch_fast_pass(p, mode, kind, fp64, s);
     const bool deriv_only = kind >= 100;
     if (deriv_only) kind = KIND_INV;
     if (fp64) {

@@ -474,10 +474,20 @@ vg_status run_program(const vg_plan* p, const Program& prog, const void* f, void
     return VG_OK;
 }
 
+int fast_pass_C(int L, int mode, bool fp64);
+
 vg_status autotune(vg_plan* p) {
-    // Built-in shapes: pencils per workgroup sized so the ping-pong LDS stays
-    // within 64 KiB where possible.
+    // Lengths with a specialised kernel use its tile width; otherwise the
+    // generic kernel's pencils per workgroup are sized so its ping-pong LDS
+    // stays within 64 KiB where possible.
     const int L = 2 * p->N;
+    const int fc = fast_pass_C(L, MODE_COL, p->fp64), fr = fast_pass_C(L, MODE_ROW, p->fp64);
+    if (fc > 0 && fr > 0 && !std::getenv("VG_GENERIC_PASSES")) {
+        p->tc.C_col = fc;
+        p->tc.C_fused = fc;
+        p->tc.C_row = fr;
+        return VG_OK;
+    }
     const size_t es = p->fp64 ? 16 : 8;
     auto pick = [&](int nbuf, int cmax) {
         int c = cmax;

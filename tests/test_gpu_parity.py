@@ -86,9 +86,10 @@ def test_plan_table_fp32_rounded_once(d, N, kernel, k):
 APPLY_CASES = [
     (3, 4, "laplace", 0.0), (3, 6, "helmholtz", 3.0), (3, 8, "helmholtz", 20.0), (3, 10, "laplace", 0.0),
     (3, 14, "helmholtz", 5.0), (3, 16, "laplace", 0.0), (3, 24, "helmholtz", 11.0), (3, 30, "helmholtz", 9.0),
-    (3, 32, "laplace", 0.0),
+    (3, 32, "laplace", 0.0), (3, 48, "helmholtz", 17.0), (3, 64, "laplace", 0.0), (3, 96, "helmholtz", 33.0),
     (2, 4, "laplace", 0.0), (2, 6, "helmholtz", 3.0), (2, 10, "laplace", 0.0), (2, 14, "helmholtz", 40.0),
     (2, 30, "laplace", 0.0), (2, 64, "helmholtz", 60.0), (2, 100, "laplace", 0.0), (2, 256, "helmholtz", 100.0),
+    (2, 48, "helmholtz", 21.0), (2, 96, "laplace", 0.0), (2, 128, "helmholtz", 75.0), (2, 512, "laplace", 0.0),
 ]
 
 
@@ -110,7 +111,9 @@ def test_apply_matches_oracle(d, N, kernel, k, precision):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("d,N,kernel,k", [(3, 8, "helmholtz", 6.0), (3, 12, "laplace", 0.0),
                                           (3, 20, "helmholtz", 13.0), (2, 16, "helmholtz", 25.0),
-                                          (2, 30, "laplace", 0.0), (2, 64, "helmholtz", 7.0)])
+                                          (2, 30, "laplace", 0.0), (2, 64, "helmholtz", 7.0),
+                                          (3, 32, "helmholtz", 10.0), (3, 48, "laplace", 0.0),
+                                          (2, 96, "helmholtz", 40.0), (2, 256, "laplace", 0.0)])
 def test_gradient_matches_oracle(d, N, kernel, k, precision):
     say("gradient", d, N, kernel, k, precision)
     vg = _vg()
@@ -172,3 +175,25 @@ def test_linearity_on_gpu():
     lhs = p.apply(c1 * a + c2 * b)
     rhs = c1 * p.apply(a) + c2 * p.apply(b)
     assert (torch.linalg.vector_norm(lhs - rhs) / torch.linalg.vector_norm(rhs)).item() < 1e-13
+
+
+@pytest.mark.parametrize("d,N,kernel,k", [(3, 32, "helmholtz", 9.0), (3, 48, "laplace", 0.0),
+                                          (2, 128, "helmholtz", 30.0), (2, 512, "helmholtz", 60.0)])
+def test_specialised_and_generic_passes_agree(d, N, kernel, k, monkeypatch):
+    """Lengths with a length-specialised kernel against the generic runtime-radix
+    kernel (selected at plan creation by VG_GENERIC_PASSES)."""
+    say("fast-vs-generic", d, N, kernel, k)
+    vg = _vg()
+    torch = _torch()
+    f = to_dev(random_density(300 + N, d, N), "fp64")
+    fast = vg.Plan(d, N, kernel, k, precision="fp64")
+    monkeypatch.setenv("VG_GENERIC_PASSES", "1")
+    gen = vg.Plan(d, N, kernel, k, precision="fp64")
+    monkeypatch.delenv("VG_GENERIC_PASSES")
+    a = fast.apply(f)
+    b = gen.apply(f)
+    ga = fast.gradient(f)[1]
+    gb = gen.gradient(f)[1]
+    torch.cuda.synchronize()
+    assert (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item() < 1e-13
+    assert (torch.linalg.vector_norm(ga - gb) / torch.linalg.vector_norm(gb)).item() < 1e-13
