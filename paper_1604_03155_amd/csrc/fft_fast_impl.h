@@ -93,6 +93,18 @@ __device__ __forceinline__ void bmap(int t, int i, int& q, int& j) {
     }
 }
 
+// Loads and stores at a uniform (scalar) base plus a 32-bit per-lane byte
+// offset: the address form global memory instructions take natively, which
+// keeps 64-bit address arithmetic off the vector ALU.
+template <typename T>
+__device__ __forceinline__ T ld_off(const void* base, unsigned off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
+template <typename T>
+__device__ __forceinline__ void st_off(void* base, unsigned off, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
+}
+
 template <int DIR, typename R>
 __device__ __forceinline__ cplx<R> twmul(cplx<R> v, cplx<R> w) {
     return DIR < 0 ? cmul(v, w) : cmulc(v, w);
@@ -114,7 +126,8 @@ __device__ __forceinline__ void compute_stage(cplx<R>* v, int t, const cplx<R>* 
             const int k = j % NS;
             constexpr int STW = L / (NS * RAD);
 #pragma unroll
-            for (int r = 1; r < RAD; ++r) v[i * RAD + r] = twmul<DIR>(v[i * RAD + r], tw[r * k * STW]);
+            for (int r = 1; r < RAD; ++r)
+                v[i * RAD + r] = twmul<DIR>(v[i * RAD + r], ld_off<cplx<R>>(tw, (unsigned)(r * k * STW) * sizeof(cplx<R>)));
         }
         dft_fixed<RAD, DIR>(&v[i * RAD]);
     }
@@ -205,79 +218,124 @@ __device__ __forceinline__ cplx<R> ikap(cplx<R> v, int e, int L, R ks) {
     return mk(-kap * v.y, kap * v.x);
 }
 
-// global -> registers for stage 0 of plan P (entries e >= NIN are zero)
+// global -> registers for stage 0 of plan P (entries e >= NIN are zero).
+// Element e = j + r L/R of pencil q: the part r (L/R) se is uniform and goes
+// into the scalar base; the lane offset (q iq + j se) * size stays below 2^32
+// (checked by the host dispatcher).  Pencils past the end of a ragged tile
+// read the tile's last pencil (in bounds; their results are never stored).
 template <typename R, int L, int C, int NT, int MODE, RP P, int NIN>
 __device__ __forceinline__ void load_global(cplx<R>* v, const cplx<R>* __restrict__ g, const FTile& tl,
                                             long long se, int t) {
     constexpr int RAD = P.r[0];
     constexpr int E = C * L / NT;
+    constexpr int LR = L / RAD;
+    unsigned off[E / RAD];
+    int jj[E / RAD];
 #pragma unroll
     for (int i = 0; i < E / RAD; ++i) {
         int q, j;
         bmap<L, C, NT, MODE, RAD>(t, i, q, j);
-        const bool ok = q < tl.nvalid;
-        const long long base = tl.in0 + q * tl.iq;
+        q = min(q, tl.nvalid - 1);
+        off[i] = (unsigned)((long long)q * tl.iq + (long long)j * se) * (unsigned)sizeof(cplx<R>);
+        jj[i] = j;
+    }
 #pragma unroll
-        for (int r = 0; r < RAD; ++r) {
-            const int e = j + r * (L / RAD);
+    for (int r = 0; r < RAD; ++r) {
+        const cplx<R>* gb = g + tl.in0 + (long long)(r * LR) * se;
+#pragma unroll
+        for (int i = 0; i < E / RAD; ++i) {
             cplx<R> x = mk(R(0), R(0));
-            if ((NIN >= L || r * (L / RAD) < NIN) && ok && e < NIN) x = g[base + (long long)e * se];
+            if ((r + 1) * LR <= NIN || (r * LR < NIN && jj[i] + r * LR < NIN)) x = ld_off<cplx<R>>(gb, off[i]);
             v[i * RAD + r] = x;
         }
     }
 }
 
-// registers (outputs of the last stage of plan P) -> global, e < NOUT only
-template <typename R, int L, int C, int NT, int MODE, RP P, int NOUT>
-__device__ __forceinline__ void store_global(const cplx<R>* v, cplx<R>* __restrict__ g, const FTile& tl,
-                                             long long se, int t) {
+// registers (outputs of the last stage of plan P) -> global, e < NOUT only.
+// Outputs never stored are dead, so their arithmetic is dropped by the compiler.
+template <typename R, int L, int C, int NT, int MODE, RP P, int NOUT, bool FULL>
+__device__ __forceinline__ void store_global_t(const cplx<R>* v, cplx<R>* __restrict__ g, const FTile& tl,
+                                               long long se, int t) {
     constexpr int RAD = P.r[P.n - 1];
     constexpr int E = C * L / NT;
+    constexpr int LR = L / RAD;
+    unsigned off[E / RAD];
+    int jj[E / RAD];
+    bool ok[E / RAD];
 #pragma unroll
     for (int i = 0; i < E / RAD; ++i) {
         int q, j;
         bmap<L, C, NT, MODE, RAD>(t, i, q, j);
-        const bool ok = q < tl.nvalid;
-        const long long base = tl.out0 + q * tl.oq;
+        ok[i] = FULL || q < tl.nvalid;
+        off[i] = (unsigned)((long long)q * tl.oq + (long long)j * se) * (unsigned)sizeof(cplx<R>);
+        jj[i] = j;
+    }
 #pragma unroll
-        for (int r = 0; r < RAD; ++r) {
-            const int e = j + r * (L / RAD);
-            if ((NOUT >= L || r * (L / RAD) < NOUT) && ok && e < NOUT) g[base + (long long)e * se] = v[i * RAD + r];
+    for (int r = 0; r < RAD; ++r) {
+        if (r * LR < NOUT) {
+            cplx<R>* gb = g + tl.out0 + (long long)(r * LR) * se;
+#pragma unroll
+            for (int i = 0; i < E / RAD; ++i)
+                if (ok[i] && ((r + 1) * LR <= NOUT || jj[i] + r * LR < NOUT)) st_off(gb, off[i], v[i * RAD + r]);
         }
     }
 }
 
-// multiply the thread's spectral values (last-stage positions of plan P) by
-// the Khat octant; d == 3: column c = k2 * L + k3, d == 2: column c = k2.
+template <typename R, int L, int C, int NT, int MODE, RP P, int NOUT>
+__device__ __forceinline__ void store_global(const cplx<R>* v, cplx<R>* __restrict__ g, const FTile& tl,
+                                             long long se, int t) {
+    if (tl.nvalid == C) store_global_t<R, L, C, NT, MODE, P, NOUT, true>(v, g, tl, se, t);
+    else store_global_t<R, L, C, NT, MODE, P, NOUT, false>(v, g, tl, se, t);
+}
+
+// Khat octant values for the thread's spectral positions (last-stage outputs
+// of plan P), loaded before the forward transform so that their latency hides
+// behind it; d == 3: column c = k2 * L + k3, d == 2: column c = k2.
 template <typename R, int L, int C, int NT, int MODE, RP P, int D, bool CPLX>
-__device__ __forceinline__ void table_mul(cplx<R>* v, const void* __restrict__ table, int tabN, int col0, int t) {
+__device__ __forceinline__ void table_fetch(cplx<R>* kt, const void* __restrict__ table, int tabN, int col0,
+                                            int nvalid, int t) {
     constexpr int RAD = P.r[P.n - 1];
     constexpr int E = C * L / NT;
     const int N1 = tabN + 1;
+    const unsigned plane = (D == 3) ? (unsigned)(N1 * N1) : (unsigned)N1;
 #pragma unroll
     for (int i = 0; i < E / RAD; ++i) {
         int q, j;
         bmap<L, C, NT, MODE, RAD>(t, i, q, j);
-        const int col = col0 + q;
-        int rowoff;
+        const int col = min(col0 + q, col0 + nvalid - 1);
+        unsigned rowoff;
         if constexpr (D == 3) {
             const int k2 = col / L, k3 = col % L;
-            rowoff = min(k2, L - k2) * N1 + min(k3, L - k3);
+            rowoff = (unsigned)(min(k2, L - k2) * N1 + min(k3, L - k3));
         } else {
-            rowoff = min(col, L - col);
+            rowoff = (unsigned)min(col, L - col);
         }
-        const long long plane = (D == 3) ? (long long)N1 * N1 : (long long)N1;
+        const unsigned jp = (unsigned)j * plane;
 #pragma unroll
         for (int r = 0; r < RAD; ++r) {
-            const int e = j + r * (L / RAD);
-            const long long flat = (long long)min(e, L - e) * plane + rowoff;
+            // e = j + r L/R with 0 <= j < L/R: the octant fold min(e, L - e) is
+            // e on blocks below L/2 and L - e on blocks at or above it.
+            constexpr int LR = L / RAD;
+            const int e = j + r * LR;
+            unsigned flat;
+            if ((r + 1) * LR <= L / 2) flat = (unsigned)(r * LR) * plane + jp + rowoff;
+            else if (r * LR >= L / 2) flat = (unsigned)(L - r * LR) * plane - jp + rowoff;
+            else flat = (unsigned)min(e, L - e) * plane + rowoff;
             if constexpr (CPLX) {
-                v[i * RAD + r] = cmul(v[i * RAD + r], reinterpret_cast<const cplx<R>*>(table)[flat]);
+                kt[i * RAD + r] = ld_off<cplx<R>>(table, flat * (unsigned)sizeof(cplx<R>));
             } else {
-                const R kv = reinterpret_cast<const R*>(table)[flat];
-                v[i * RAD + r] = mk(v[i * RAD + r].x * kv, v[i * RAD + r].y * kv);
+                kt[i * RAD + r] = mk(ld_off<R>(table, flat * (unsigned)sizeof(R)), R(0));
             }
         }
+    }
+}
+
+template <typename R, int E, bool CPLX>
+__device__ __forceinline__ void table_apply(cplx<R>* v, const cplx<R>* kt) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        if constexpr (CPLX) v[e] = cmul(v[e], kt[e]);
+        else v[e] = mk(v[e].x * kt[e].x, v[e].y * kt[e].x);
     }
 }
 
@@ -337,9 +395,11 @@ __global__ void __launch_bounds__(NT) fast_kernel(PassDesc p) {
         store_global<R, L, C, NT, MODE, I, L / 2>(w, gout2, tl, p.out_se, t);
     } else {
         // FK_FUSED, FK_FUSED_GRAD
+        cplx<R> kt[E];
         load_global<R, L, C, NT, MODE, F, L / 2>(v, gin, tl, p.in_se, t);
+        table_fetch<R, L, C, NT, MODE, F, D, CPLX>(kt, p.table, p.tabN, tl.col0, tl.nvalid, t);
         run_from<R, L, C, NT, MODE, -1, F, 0>(v, lds, t, tw);
-        table_mul<R, L, C, NT, MODE, F, D, CPLX>(v, p.table, p.tabN, tl.col0, t);
+        table_apply<R, E, CPLX>(v, kt);
         if constexpr (FK == FK_FUSED) {
             run_from<R, L, C, NT, MODE, +1, I, 0>(v, lds, t, tw);
             store_global<R, L, C, NT, MODE, I, L / 2>(v, gout, tl, p.out_se, t);
