@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--workload", default="helmholtz3d_k20_n256")
     ap.add_argument("--cpu-sample", type=int, default=3, help="oracle applies timed for cpu_baseline (0: skip)")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--hbm-copy-mib", type=int, default=0,
+                    help="after timing, run one streaming copy of this many MiB (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -111,6 +113,14 @@ def main():
     ms_per_step = 1e3 * seconds / args.steps
     value = V * args.steps / seconds
     log(f"[bench] {ms_per_step:.3f} ms/step, {value:.3e} grid pts/s")
+
+    if args.hbm_copy_mib > 0:
+        nb = args.hbm_copy_mib << 20
+        src_b = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        dst_b = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        vg.hbm_copy(dst_b, src_b)
+        torch.cuda.synchronize()
+        del src_b, dst_b
 
     pass_rows = []
     for p in passes:

@@ -1,7 +1,9 @@
-// Small DFT kernels ("butterflies") of radix 2, 3, 4, 5, 7 and 8 used by the
-// Stockham FFT passes.  DIR = -1 computes y_m = sum_r v_r e^{-2 pi i r m / R}
+// Small DFT kernels ("butterflies") of radix 2, 3, 4, 5, 7, 8, 16 and 32 used
+// by the Stockham FFT passes.  DIR = -1 computes y_m = sum_r v_r e^{-2 pi i r m / R}
 // (forward), DIR = +1 the conjugate-exponent sum (inverse, unnormalised).
 #pragma once
+
+#include <utility>
 
 #include "common.h"
 
@@ -128,6 +130,86 @@ __device__ __forceinline__ void dft_any(int radix, cplx<R>* v) {
     }
 }
 
+// ------------------------------------------------ radix 16 and 32 --------
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    [&]<int... I>(std::integer_sequence<int, I...>) { (f(std::integral_constant<int, I>{}), ...); }
+    (std::make_integer_sequence<int, N>{});
+}
+
+// cos(2 pi k / 32) for k = 0..8; other angles follow by symmetry.
+constexpr double kCos32[9] = {1.0,
+                              0.98078528040323044912618,
+                              0.92387953251128675612818,
+                              0.83146961230254523707879,
+                              0.70710678118654752440084,
+                              0.55557023301960222474283,
+                              0.38268343236508977172846,
+                              0.19509032201612826784828,
+                              0.0};
+
+constexpr double cos32(int k) {
+    k = ((k % 32) + 32) % 32;
+    if (k <= 8) return kCos32[k];
+    if (k <= 16) return -kCos32[16 - k];
+    if (k <= 24) return -kCos32[k - 16];
+    return kCos32[32 - k];
+}
+constexpr double sin32(int k) { return cos32(k - 8); }
+
+// v * e^{DIR 2 pi i m / RR} for a compile-time m (RR divides 32); the four
+// axis-aligned cases cost no multiplications.
+template <int RR, int m, int DIR, typename R>
+__device__ __forceinline__ cplx<R> wmul_const(cplx<R> v) {
+    constexpr int mm = ((m % RR) + RR) % RR;
+    if constexpr (mm == 0) {
+        return v;
+    } else if constexpr (4 * mm == RR) {
+        return mul_diri<DIR>(v);
+    } else if constexpr (2 * mm == RR) {
+        return mk(-v.x, -v.y);
+    } else if constexpr (4 * mm == 3 * RR) {
+        return mul_diri<-DIR>(v);
+    } else {
+        constexpr int k = mm * (32 / RR);
+        constexpr R c = R(cos32(k));
+        constexpr R sn = R(DIR * sin32(k));
+        return mk(v.x * c - v.y * sn, v.y * c + v.x * sn);
+    }
+}
+
+template <int RAD, int DIR, typename R>
+__device__ __forceinline__ void dft_fixed(cplx<R>* v);
+
+// DFT of size R1*R2 in registers (Cooley-Tukey): R1 DFTs of size R2 over
+// stride-R1 subsequences, twiddles W_{R1 R2}^{n1 k2}, R2 DFTs of size R1;
+// output index k2 + R2 k1.
+template <int R1, int R2, int DIR, typename R>
+__device__ __forceinline__ void dft_ct(cplx<R>* v) {
+    constexpr int RR = R1 * R2;
+    cplx<R> a[RR];
+    static_for<R1>([&](auto n1c) {
+        constexpr int n1 = decltype(n1c)::value;
+        cplx<R> s[R2];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) s[n2] = v[n1 + R1 * n2];
+        dft_fixed<R2, DIR>(s);
+        static_for<R2>([&](auto k2c) {
+            constexpr int k2 = decltype(k2c)::value;
+            a[n1 * R2 + k2] = wmul_const<RR, n1 * k2, DIR>(s[k2]);
+        });
+    });
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) {
+        cplx<R> s[R1];
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) s[n1] = a[n1 * R2 + k2];
+        dft_fixed<R1, DIR>(s);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) v[k2 + R2 * k1] = s[k1];
+    }
+}
+
 // Compile-time radix dispatch.
 template <int RAD, int DIR, typename R>
 __device__ __forceinline__ void dft_fixed(cplx<R>* v) {
@@ -136,7 +218,10 @@ __device__ __forceinline__ void dft_fixed(cplx<R>* v) {
     else if constexpr (RAD == 4) dft4<DIR>(v[0], v[1], v[2], v[3]);
     else if constexpr (RAD == 5) dft5<DIR>(v);
     else if constexpr (RAD == 7) dft7<DIR>(v);
-    else dft8<DIR>(v);
+    else if constexpr (RAD == 8) dft8<DIR>(v);
+    else if constexpr (RAD == 16) dft_ct<4, 4, DIR>(v);
+    else if constexpr (RAD == 32) dft_ct<4, 8, DIR>(v);
+    else static_assert(RAD == 2, "unsupported radix");
 }
 
 }  // namespace vg

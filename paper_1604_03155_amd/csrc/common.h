@@ -74,6 +74,7 @@ struct PassDesc {
     int inner;              // columns per outer block (MODE_COL); 1 for rows
     int outer;              // outer blocks (MODE_COL) or pencils (MODE_ROW)
     int C;                  // pencils per workgroup
+    int variant;            // launch-shape variant of the specialised kernels (0 = default)
     int nst;
     int radix[kMaxStages];
     // Khat octant indexing for fused kinds: the pencil's other spectral

@@ -5,6 +5,8 @@
 // E = C L / NT values in registers; a Stockham stage of radix R runs E/R
 // butterflies per thread on registers, and consecutive stages exchange data
 // through ONE LDS buffer of C L values (store, barrier, load, barrier).
+// Complex64 power-of-two lengths use radices up to 32 (512 = 32 x 16), so a
+// transform needs one LDS exchange instead of two.
 //
 // Fusion.  The last forward stage leaves the thread holding exactly the
 // spectral values its first inverse butterflies need (the inverse uses the
@@ -31,7 +33,11 @@ struct RP {
     int r[kMaxStages];
 };
 
-constexpr RP make_plan(int L) {
+// Radix plan of a specialised length.  Power-of-two lengths take as few
+// stages as radices up to MAXR allow, with the bits spread evenly (512 =
+// 32 x 16 for complex64); lengths with factors 3, 5, 7 use radices up to 8
+// and one stage per odd factor.
+constexpr RP make_plan(int L, int maxr = 8) {
     RP p{};
     p.n = 0;
     int x = L, a = 0;
@@ -39,12 +45,14 @@ constexpr RP make_plan(int L) {
         x /= 2;
         ++a;
     }
-    while (a >= 3) {
-        p.r[p.n++] = 8;
-        a -= 3;
+    int mb = 3;  // bits per power-of-two stage
+    if (x == 1) mb = maxr >= 32 ? 5 : (maxr >= 16 ? 4 : 3);
+    const int S = (a + mb - 1) / mb;
+    for (int i = 0; i < S; ++i) {
+        const int bits = a / (S - i) + ((a % (S - i)) ? 1 : 0);
+        p.r[p.n++] = 1 << bits;
+        a -= bits;
     }
-    if (a == 2) p.r[p.n++] = 4;
-    if (a == 1) p.r[p.n++] = 2;
     const int odd[3] = {3, 5, 7};
     for (int i = 0; i < 3; ++i)
         while (x % odd[i] == 0) {
@@ -53,6 +61,10 @@ constexpr RP make_plan(int L) {
         }
     return p;
 }
+
+// largest radix used for a precision: complex64 threads hold 32 values
+template <typename R>
+constexpr int kMaxRad = sizeof(R) == 4 ? 32 : 16;
 
 constexpr RP reversed(RP p) {
     RP q{};
@@ -177,13 +189,14 @@ struct FTile {
     int col0;
 };
 
+// XCD-aware order for one-tile-per-workgroup launches: dispatch slot b runs
+// on XCD b % 8; give each XCD a contiguous range of tiles.
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb) {
+    return ((nb & 7u) == 0u) ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
+}
+
 template <int C, int MODE>
-__device__ __forceinline__ FTile fast_tile(const PassDesc& p) {
-    // XCD-aware permutation: dispatch slot b runs on XCD b % 8; give each XCD a
-    // contiguous range of tiles.
-    const unsigned nb = gridDim.x;
-    unsigned b = blockIdx.x;
-    if ((nb & 7u) == 0u) b = (b & 7u) * (nb >> 3) + (b >> 3);
+__device__ __forceinline__ FTile fast_tile(const PassDesc& p, unsigned b) {
     FTile t;
     if constexpr (MODE == MODE_COL) {
         const int ntile = (p.inner + C - 1) / C;
@@ -223,16 +236,26 @@ __device__ __forceinline__ cplx<R> ikap(cplx<R> v, int e, int L, R ks) {
 // into the scalar base; the lane offset (q iq + j se) * size stays below 2^32
 // (checked by the host dispatcher).  Pencils past the end of a ragged tile
 // read the tile's last pencil (in bounds; their results are never stored).
+// Only blocks r with r L/R < NIN are loaded (NR of them); expand() places the
+// loaded values and the zeros into stage order.
+template <typename R, int L, int C, int NT, RP P, int NIN>
+struct LoadSet {
+    static constexpr int RAD = P.r[0];
+    static constexpr int E = C * L / NT;
+    static constexpr int LR = L / RAD;
+    static constexpr int NR = ((NIN + LR - 1) / LR) < RAD ? (NIN + LR - 1) / LR : RAD;
+    static constexpr int NV = (E / RAD) * NR;
+};
+
 template <typename R, int L, int C, int NT, int MODE, RP P, int NIN>
-__device__ __forceinline__ void load_global(cplx<R>* v, const cplx<R>* __restrict__ g, const FTile& tl,
+__device__ __forceinline__ void issue_loads(cplx<R>* vn, const cplx<R>* __restrict__ g, const FTile& tl,
                                             long long se, int t) {
-    constexpr int RAD = P.r[0];
-    constexpr int E = C * L / NT;
-    constexpr int LR = L / RAD;
-    unsigned off[E / RAD];
-    int jj[E / RAD];
+    using LS = LoadSet<R, L, C, NT, P, NIN>;
+    constexpr int RAD = LS::RAD, LR = LS::LR, NR = LS::NR, NB = LS::E / RAD;
+    unsigned off[NB];
+    int jj[NB];
 #pragma unroll
-    for (int i = 0; i < E / RAD; ++i) {
+    for (int i = 0; i < NB; ++i) {
         int q, j;
         bmap<L, C, NT, MODE, RAD>(t, i, q, j);
         q = min(q, tl.nvalid - 1);
@@ -240,15 +263,25 @@ __device__ __forceinline__ void load_global(cplx<R>* v, const cplx<R>* __restric
         jj[i] = j;
     }
 #pragma unroll
-    for (int r = 0; r < RAD; ++r) {
+    for (int r = 0; r < NR; ++r) {
         const cplx<R>* gb = g + tl.in0 + (long long)(r * LR) * se;
 #pragma unroll
-        for (int i = 0; i < E / RAD; ++i) {
+        for (int i = 0; i < NB; ++i) {
             cplx<R> x = mk(R(0), R(0));
-            if ((r + 1) * LR <= NIN || (r * LR < NIN && jj[i] + r * LR < NIN)) x = ld_off<cplx<R>>(gb, off[i]);
-            v[i * RAD + r] = x;
+            if ((r + 1) * LR <= NIN || jj[i] + r * LR < NIN) x = ld_off<cplx<R>>(gb, off[i]);
+            vn[i * NR + r] = x;
         }
     }
+}
+
+template <typename R, int L, int C, int NT, RP P, int NIN>
+__device__ __forceinline__ void expand(cplx<R>* v, const cplx<R>* vn) {
+    using LS = LoadSet<R, L, C, NT, P, NIN>;
+    constexpr int RAD = LS::RAD, NR = LS::NR, NB = LS::E / RAD;
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) v[i * RAD + r] = r < NR ? vn[i * NR + r] : mk(R(0), R(0));
 }
 
 // registers (outputs of the last stage of plan P) -> global, e < NOUT only.
@@ -355,27 +388,29 @@ __device__ __forceinline__ void deriv_copy(const cplx<R>* v, cplx<R>* v2, R ks, 
 
 enum FastKind : int { FK_FWD = 0, FK_INV = 1, FK_FUSED = 2, FK_FUSED_GRAD = 3, FK_INV_GRAD = 4, FK_INV_DERIV = 5 };
 
+template <int FK>
+struct KindIO {
+    // forward kinds load zero-padded pencils with the forward plan; inverse
+    // kinds load full spectral pencils with the reversed plan
+    static constexpr bool fwd_load = FK == FK_FWD || FK == FK_FUSED || FK == FK_FUSED_GRAD;
+};
+
+// Everything after the stage-0 loads of one tile: transforms, multiplies,
+// stores.  v holds the stage-0 inputs; kt the Khat values (fused kinds).
 template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX>
-__global__ void __launch_bounds__(NT) fast_kernel(PassDesc p) {
-    constexpr RP F = make_plan(L);
+__device__ __forceinline__ void tile_body(cplx<R>* v, cplx<R>* kt, cplx<R>* lds, const FTile& tl,
+                                          const PassDesc& p, int t) {
+    constexpr RP F = make_plan(L, kMaxRad<R>);
     constexpr RP I = reversed(F);
     constexpr int E = C * L / NT;
-    using LY = Lay<L, C, MODE>;
-    __shared__ cplx<R> lds[LY::size];
-    const int t = threadIdx.x;
-    const FTile tl = fast_tile<C, MODE>(p);
     const cplx<R>* __restrict__ tw = reinterpret_cast<const cplx<R>*>(p.tw);
-    const cplx<R>* __restrict__ gin = reinterpret_cast<const cplx<R>*>(p.in);
     cplx<R>* __restrict__ gout = reinterpret_cast<cplx<R>*>(p.out);
     cplx<R>* __restrict__ gout2 = reinterpret_cast<cplx<R>*>(p.out2);
     const R ks = (R)p.kscale;
-    cplx<R> v[E];
     if constexpr (FK == FK_FWD) {
-        load_global<R, L, C, NT, MODE, F, L / 2>(v, gin, tl, p.in_se, t);
         run_from<R, L, C, NT, MODE, -1, F, 0>(v, lds, t, tw);
         store_global<R, L, C, NT, MODE, F, L>(v, gout, tl, p.out_se, t);
     } else if constexpr (FK == FK_INV || FK == FK_INV_DERIV) {
-        load_global<R, L, C, NT, MODE, I, L>(v, gin, tl, p.in_se, t);
         if constexpr (FK == FK_INV_DERIV) {
             cplx<R> w[E];
             deriv_copy<R, L, C, NT, MODE, I.r[0]>(v, w, ks, t);
@@ -385,7 +420,6 @@ __global__ void __launch_bounds__(NT) fast_kernel(PassDesc p) {
         run_from<R, L, C, NT, MODE, +1, I, 0>(v, lds, t, tw);
         store_global<R, L, C, NT, MODE, I, L / 2>(v, gout, tl, p.out_se, t);
     } else if constexpr (FK == FK_INV_GRAD) {
-        load_global<R, L, C, NT, MODE, I, L>(v, gin, tl, p.in_se, t);
         cplx<R> w[E];
         deriv_copy<R, L, C, NT, MODE, I.r[0]>(v, w, ks, t);
         run_from<R, L, C, NT, MODE, +1, I, 0>(v, lds, t, tw);
@@ -394,10 +428,6 @@ __global__ void __launch_bounds__(NT) fast_kernel(PassDesc p) {
         run_from<R, L, C, NT, MODE, +1, I, 0>(w, lds, t, tw);
         store_global<R, L, C, NT, MODE, I, L / 2>(w, gout2, tl, p.out_se, t);
     } else {
-        // FK_FUSED, FK_FUSED_GRAD
-        cplx<R> kt[E];
-        load_global<R, L, C, NT, MODE, F, L / 2>(v, gin, tl, p.in_se, t);
-        table_fetch<R, L, C, NT, MODE, F, D, CPLX>(kt, p.table, p.tabN, tl.col0, tl.nvalid, t);
         run_from<R, L, C, NT, MODE, -1, F, 0>(v, lds, t, tw);
         table_apply<R, E, CPLX>(v, kt);
         if constexpr (FK == FK_FUSED) {
@@ -415,46 +445,64 @@ __global__ void __launch_bounds__(NT) fast_kernel(PassDesc p) {
     }
 }
 
+// One tile per workgroup.
+template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX>
+__global__ void __launch_bounds__(NT) fast_kernel(PassDesc p) {
+    constexpr RP F = make_plan(L, kMaxRad<R>);
+    constexpr RP I = reversed(F);
+    constexpr int E = C * L / NT;
+    constexpr bool FL = KindIO<FK>::fwd_load;
+    constexpr RP PL = FL ? F : I;
+    constexpr int NIN = FL ? L / 2 : L;
+    using LY = Lay<L, C, MODE>;
+    __shared__ cplx<R> lds[LY::size];
+    const int t = threadIdx.x;
+    const FTile tl = fast_tile<C, MODE>(p, xcd_tile(blockIdx.x, gridDim.x));
+    const cplx<R>* __restrict__ gin = reinterpret_cast<const cplx<R>*>(p.in);
+    cplx<R> vn[LoadSet<R, L, C, NT, PL, NIN>::NV];
+    cplx<R> v[E];
+    cplx<R> kt[(FK == FK_FUSED || FK == FK_FUSED_GRAD) ? E : 1];
+    issue_loads<R, L, C, NT, MODE, PL, NIN>(vn, gin, tl, p.in_se, t);
+    if constexpr (FK == FK_FUSED || FK == FK_FUSED_GRAD)
+        table_fetch<R, L, C, NT, MODE, F, D, CPLX>(kt, p.table, p.tabN, tl.col0, tl.nvalid, t);
+    expand<R, L, C, NT, PL, NIN>(v, vn);
+    tile_body<R, L, C, NT, MODE, FK, D, CPLX>(v, kt, lds, tl, p, t);
+}
+
 // --------------------------------------------------------------- dispatch --
+template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX>
+hipError_t launch_k(const PassDesc& p, long long ntiles, hipStream_t s) {
+    hipLaunchKernelGGL((fast_kernel<R, L, C, NT, MODE, FK, D, CPLX>), dim3((unsigned)ntiles), dim3(NT), 0, s, p);
+    return hipGetLastError();
+}
+
 template <typename R, int L, int C, int NT, int MODE>
 hipError_t launch_shape(const PassDesc& p, int kind, hipStream_t s) {
     long long nblocks = MODE == MODE_COL ? (long long)p.outer * ((p.inner + C - 1) / C) : (p.outer + C - 1) / C;
     if (nblocks <= 0) return hipSuccess;
     if (nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    const dim3 grid((unsigned)nblocks), block(NT);
     const bool fused = kind == KIND_FUSED || kind == KIND_FUSED_GRAD;
     if (fused && MODE == MODE_COL) {
         const bool g = kind == KIND_FUSED_GRAD;
-#define VG_FUSED_LAUNCH(DD, CX)                                                                          \
-    if (g) {                                                                                             \
-        hipLaunchKernelGGL((fast_kernel<R, L, C, NT, MODE, FK_FUSED_GRAD, DD, CX>), grid, block, 0, s, p); \
-    } else {                                                                                             \
-        hipLaunchKernelGGL((fast_kernel<R, L, C, NT, MODE, FK_FUSED, DD, CX>), grid, block, 0, s, p);      \
-    }
-        if (p.d == 3 && p.table_complex) {
-            VG_FUSED_LAUNCH(3, true)
-        } else if (p.d == 3) {
-            VG_FUSED_LAUNCH(3, false)
-        } else if (p.table_complex) {
-            VG_FUSED_LAUNCH(2, true)
-        } else {
-            VG_FUSED_LAUNCH(2, false)
-        }
-#undef VG_FUSED_LAUNCH
-        return hipGetLastError();
+        if (p.d == 3 && p.table_complex)
+            return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 3, true>(p, nblocks, s)
+                     : launch_k<R, L, C, NT, MODE, FK_FUSED, 3, true>(p, nblocks, s);
+        if (p.d == 3)
+            return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 3, false>(p, nblocks, s)
+                     : launch_k<R, L, C, NT, MODE, FK_FUSED, 3, false>(p, nblocks, s);
+        if (p.table_complex)
+            return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 2, true>(p, nblocks, s)
+                     : launch_k<R, L, C, NT, MODE, FK_FUSED, 2, true>(p, nblocks, s);
+        return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 2, false>(p, nblocks, s)
+                 : launch_k<R, L, C, NT, MODE, FK_FUSED, 2, false>(p, nblocks, s);
     }
     switch (kind) {
-        case KIND_FWD: hipLaunchKernelGGL((fast_kernel<R, L, C, NT, MODE, FK_FWD, 3, false>), grid, block, 0, s, p); break;
-        case KIND_INV: hipLaunchKernelGGL((fast_kernel<R, L, C, NT, MODE, FK_INV, 3, false>), grid, block, 0, s, p); break;
-        case KIND_INV_GRAD:
-            hipLaunchKernelGGL((fast_kernel<R, L, C, NT, MODE, FK_INV_GRAD, 3, false>), grid, block, 0, s, p);
-            break;
-        case 100 + KIND_INV:
-            hipLaunchKernelGGL((fast_kernel<R, L, C, NT, MODE, FK_INV_DERIV, 3, false>), grid, block, 0, s, p);
-            break;
+        case KIND_FWD: return launch_k<R, L, C, NT, MODE, FK_FWD, 3, false>(p, nblocks, s);
+        case KIND_INV: return launch_k<R, L, C, NT, MODE, FK_INV, 3, false>(p, nblocks, s);
+        case KIND_INV_GRAD: return launch_k<R, L, C, NT, MODE, FK_INV_GRAD, 3, false>(p, nblocks, s);
+        case 100 + KIND_INV: return launch_k<R, L, C, NT, MODE, FK_INV_DERIV, 3, false>(p, nblocks, s);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 // Launch shape per (length, mode, element size): C pencils per workgroup, E
@@ -468,7 +516,7 @@ struct Shape {
 constexpr int gcd_i(int a, int b) { return b == 0 ? a : gcd_i(b, a % b); }
 
 constexpr Shape shape_for(int L, int mode, int esize) {
-    const RP p = make_plan(L);
+    const RP p = make_plan(L, esize == 8 ? 32 : 16);
     int lc = 1;
     for (int i = 0; i < p.n; ++i) lc = lc / gcd_i(lc, p.r[i]) * p.r[i];
     const int target = esize == 16 ? 16 : 32;

@@ -368,9 +368,13 @@ void set_ws(Program& prog, const std::vector<size_t>& sizes_bytes) {
 
 void finalize_bytes(vg_plan* p);
 
+// Intermediate layouts.  A column tile whose rows are a large power of two
+// apart (a whole 2N x 2N plane in 3D, a 2N row in 2D) keeps hitting the same
+// HBM channels, so those pitches are lengthened by 256 bytes.
 void build_programs(vg_plan* p) {
     const long long N = p->N, L = 2 * N;
     const size_t es = p->fp64 ? 16 : 8;
+    const long long PAD = 256 / (long long)es;
     const int W0 = BUF_WS0, W1 = BUF_WS0 + 1, W2 = BUF_WS0 + 2, W3 = BUF_WS0 + 3, W4 = BUF_WS0 + 4;
     Program& A = p->apply_prog;
     Program& G = p->grad_prog;
@@ -378,41 +382,45 @@ void build_programs(vg_plan* p) {
     G.steps.clear();
     if (p->d == 3) {
         const long long V = N * N * N;
+        const long long PL = L * L + PAD;   // plane pitch of the [N][L][L] intermediates
+        const long long PS = N * L;         // [N][N][L] intermediates stay dense (pencil stride L)
+        const size_t b2 = (size_t)(N * PS) * es, b4 = (size_t)(N * PL) * es;
         // apply: f -(rows, axis 3)-> W0[N][N][L] -(axis 2)-> W1[N][L][L]
         //        -(axis 1: fwd, Khat, inv, crop; in place)-> W1
         //        -(axis 2 inverse, crop)-> W0[N][N][L] -(rows inverse, crop)-> phi
-        set_ws(A, {(size_t)(2 * V) * es, (size_t)(4 * V) * es});
+        set_ws(A, {b2, b4});
         A.steps.push_back(row_step(p, KIND_FWD, BUF_F, N, (int)N, W0, L, (int)L, N * N, "p1_row_fwd"));
-        A.steps.push_back(col_step(p, KIND_FWD, W0, N * L, L, (int)N, W1, L * L, L, (int)L, L, N, "p2_col_fwd"));
-        A.steps.push_back(col_step(p, KIND_FUSED, W1, 0, L * L, (int)N, W1, 0, L * L, (int)N, L * L, 1, "p3_fused"));
-        A.steps.push_back(col_step(p, KIND_INV, W1, L * L, L, (int)L, W0, N * L, L, (int)N, L, N, "p4_col_inv"));
+        A.steps.push_back(col_step(p, KIND_FWD, W0, PS, L, (int)N, W1, PL, L, (int)L, L, N, "p2_col_fwd"));
+        A.steps.push_back(col_step(p, KIND_FUSED, W1, 0, PL, (int)N, W1, 0, PL, (int)N, L * L, 1, "p3_fused"));
+        A.steps.push_back(col_step(p, KIND_INV, W1, PL, L, (int)L, W0, PS, L, (int)N, L, N, "p4_col_inv"));
         A.steps.push_back(row_step(p, KIND_INV, W0, L, (int)L, BUF_PHI, N, (int)N, N * N, "p5_row_inv"));
         // gradient: W0 (2V), W1 (4V), W2 (4V), W3 (2V), W4 (2V)
-        set_ws(G, {(size_t)(2 * V) * es, (size_t)(4 * V) * es, (size_t)(4 * V) * es, (size_t)(2 * V) * es,
-                   (size_t)(2 * V) * es});
+        set_ws(G, {b2, b4, b4, b2, b2});
         G.steps.push_back(row_step(p, KIND_FWD, BUF_F, N, (int)N, W0, L, (int)L, N * N, "g1_row_fwd"));
-        G.steps.push_back(col_step(p, KIND_FWD, W0, N * L, L, (int)N, W1, L * L, L, (int)L, L, N, "g2_col_fwd"));
-        G.steps.push_back(col_step(p, KIND_FUSED_GRAD, W1, 0, L * L, (int)N, W1, 0, L * L, (int)N, L * L, 1,
+        G.steps.push_back(col_step(p, KIND_FWD, W0, PS, L, (int)N, W1, PL, L, (int)L, L, N, "g2_col_fwd"));
+        G.steps.push_back(col_step(p, KIND_FUSED_GRAD, W1, 0, PL, (int)N, W1, 0, PL, (int)N, L * L, 1,
                                    "g3_fused_grad", W2));
-        G.steps.push_back(col_step(p, KIND_INV_GRAD, W1, L * L, L, (int)L, W0, N * L, L, (int)N, L, N,
+        G.steps.push_back(col_step(p, KIND_INV_GRAD, W1, PL, L, (int)L, W0, PS, L, (int)N, L, N,
                                    "g4_col_inv_grad", W3));
-        G.steps.push_back(col_step(p, KIND_INV, W2, L * L, L, (int)L, W4, N * L, L, (int)N, L, N, "g4_col_inv"));
+        G.steps.push_back(col_step(p, KIND_INV, W2, PL, L, (int)L, W4, PS, L, (int)N, L, N, "g4_col_inv"));
         G.steps.push_back(row_step(p, KIND_INV_GRAD, W0, L, (int)L, BUF_PHI, N, (int)N, N * N, "g5_row_inv_grad",
                                    BUF_GRAD0 + 2));
         G.steps.push_back(row_step(p, KIND_INV, W3, L, (int)L, BUF_GRAD0 + 1, N, (int)N, N * N, "g5_row_inv_d2"));
         G.steps.push_back(row_step(p, KIND_INV, W4, L, (int)L, BUF_GRAD0 + 0, N, (int)N, N * N, "g5_row_inv_d1"));
+        (void)V;
     } else {
-        const long long V = N * N;
-        set_ws(A, {(size_t)(2 * V) * es});
-        A.steps.push_back(row_step(p, KIND_FWD, BUF_F, N, (int)N, W0, L, (int)L, N, "p1_row_fwd"));
-        A.steps.push_back(col_step(p, KIND_FUSED, W0, 0, L, (int)N, W0, 0, L, (int)N, L, 1, "p2_fused"));
-        A.steps.push_back(row_step(p, KIND_INV, W0, L, (int)L, BUF_PHI, N, (int)N, N, "p3_row_inv"));
-        set_ws(G, {(size_t)(2 * V) * es, (size_t)(2 * V) * es});
-        G.steps.push_back(row_step(p, KIND_FWD, BUF_F, N, (int)N, W0, L, (int)L, N, "g1_row_fwd"));
-        G.steps.push_back(col_step(p, KIND_FUSED_GRAD, W0, 0, L, (int)N, W0, 0, L, (int)N, L, 1, "g2_fused_grad", W1));
-        G.steps.push_back(row_step(p, KIND_INV_GRAD, W0, L, (int)L, BUF_PHI, N, (int)N, N, "g3_row_inv_grad",
+        const long long RP = L + PAD;  // row pitch of the [N][L] intermediates
+        const size_t b2 = (size_t)(N * RP) * es;
+        set_ws(A, {b2});
+        A.steps.push_back(row_step(p, KIND_FWD, BUF_F, N, (int)N, W0, RP, (int)L, N, "p1_row_fwd"));
+        A.steps.push_back(col_step(p, KIND_FUSED, W0, 0, RP, (int)N, W0, 0, RP, (int)N, L, 1, "p2_fused"));
+        A.steps.push_back(row_step(p, KIND_INV, W0, RP, (int)L, BUF_PHI, N, (int)N, N, "p3_row_inv"));
+        set_ws(G, {b2, b2});
+        G.steps.push_back(row_step(p, KIND_FWD, BUF_F, N, (int)N, W0, RP, (int)L, N, "g1_row_fwd"));
+        G.steps.push_back(col_step(p, KIND_FUSED_GRAD, W0, 0, RP, (int)N, W0, 0, RP, (int)N, L, 1, "g2_fused_grad", W1));
+        G.steps.push_back(row_step(p, KIND_INV_GRAD, W0, RP, (int)L, BUF_PHI, N, (int)N, N, "g3_row_inv_grad",
                                    BUF_GRAD0 + 1));
-        G.steps.push_back(row_step(p, KIND_INV, W1, L, (int)L, BUF_GRAD0 + 0, N, (int)N, N, "g3_row_inv_d1"));
+        G.steps.push_back(row_step(p, KIND_INV, W1, RP, (int)L, BUF_GRAD0 + 0, N, (int)N, N, "g3_row_inv_d1"));
     }
     finalize_bytes(p);
 }
