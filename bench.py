@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_helmholtz3d_k20_n256.json")
-KERNEL_SOURCES = ["fft_pass.hip", "butterfly.h", "common.h"]
+KERNEL_SOURCES = ["fft_fast_impl.h", "fft_fast_512.hip", "butterfly.h", "common.h", "fft_pass.hip"]
 
 
 def log(*a):

@@ -129,7 +129,9 @@ def test_gradient_matches_oracle(d, N, kernel, k, precision):
     gref = o.gradient(f)
     for j in range(d):
         assert rel_l2(grad[j].cpu().numpy(), gref[j]) <= tol, j
-    assert torch.equal(grad, grad_only)
+    # the phi-less call runs a derivative-only kernel: same result to rounding
+    agree = (torch.linalg.vector_norm(grad - grad_only) / torch.linalg.vector_norm(grad)).item()
+    assert agree <= (1e-14 if precision == "fp64" else 1e-6)
 
 
 def test_in_place_and_zero_density():
