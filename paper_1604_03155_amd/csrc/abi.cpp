@@ -10,7 +10,6 @@
 namespace vg {
 const char* last_error_cstr();
 vg_status precompute(vg_plan* p, hipStream_t s, bool keep_T);
-vg_status make_twiddles(vg_plan* p, hipStream_t s);
 vg_status batched_apply(int count, const vg_plan* const* plans, const void* const* f, void* const* phi,
                         void* workspace, hipStream_t stream);
 size_t batched_workspace_size(int count, const vg_plan* const* plans);
@@ -25,7 +24,8 @@ namespace {
 void free_plan(vg_plan* p) {
     if (!p) return;
     batched_release_plan(p);
-    if (p->twiddle) (void)hipFree(p->twiddle);
+    for (auto& kv : p->twiddles)
+        if (kv.second) (void)hipFree(kv.second);
     if (p->table) (void)hipFree(p->table);
     if (p->T_dev) (void)hipFree(p->T_dev);
     if (p->internal_ws) (void)hipFree(p->internal_ws);
@@ -104,10 +104,6 @@ vg_status vg_plan_create_ex(int d, int N, vg_kernel kernel, double k, const vg_p
         if (d == 2 && N > 16384) return fail(VG_ERR_UNSUPPORTED_SIZE, "N too large for 2D");
         vg_status st = check_device();
         if (st != VG_OK) return st;
-        const size_t esz = o.precision == VG_FP64 ? 16 : 8;
-        // a column pass must hold at least 3 pencils of length 2N in LDS
-        if ((size_t)3 * 2 * N * esz > (size_t)fft_max_lds_bytes_for_device())
-            return fail(VG_ERR_UNSUPPORTED_SIZE, "2N too long for a single LDS-resident pencil");
 
         std::unique_ptr<vg_plan, void (*)(vg_plan*)> p(new vg_plan(), free_plan);
         p->d = d;
@@ -120,16 +116,14 @@ vg_status vg_plan_create_ex(int d, int N, vg_kernel kernel, double k, const vg_p
         p->fp64 = o.precision == VG_FP64;
         p->tune = o.tune;
         p->radices = rad;
+        p->table_complex = (kernel == VG_HELMHOLTZ) ? 1 : 0;
         hipError_t he = hipGetDevice(&p->device);
         if (he != hipSuccess) return from_hip(he, "hipGetDevice");
         hipStream_t s = reinterpret_cast<hipStream_t>(o.stream);
-        st = make_twiddles(p.get(), s);
+        st = build_programs(p.get(), s);  // rejects sizes no pass kernel can run
         if (st != VG_OK) return st;
         st = precompute(p.get(), s, o.keep_operator != 0);
         if (st != VG_OK) return st;
-        st = autotune(p.get());
-        if (st != VG_OK) return st;
-        build_programs(p.get());
         *out = p.release();
         return VG_OK;
     });

@@ -74,7 +74,7 @@ struct PassDesc {
     int inner;              // columns per outer block (MODE_COL); 1 for rows
     int outer;              // outer blocks (MODE_COL) or pencils (MODE_ROW)
     int C;                  // pencils per workgroup
-    int variant;            // launch-shape variant of the specialised kernels (0 = default)
+    int specialised;        // 1: run the length-specialised kernel (chosen at plan time)
     int nst;
     int radix[kMaxStages];
     // Khat octant indexing for fused kinds: the pencil's other spectral
@@ -83,8 +83,17 @@ struct PassDesc {
     int tabN;               // N of the plan (octant is (N+1)^d)
     int table_complex;      // 0: real table (Laplace), 1: complex
     // spectral derivative along this pass's axis (gradient kinds): i*kappa,
-    // kappa = kscale * signed(e), zero at the Nyquist index e = L/2.
+    // kappa = kscale * signed(k), zero at the Nyquist index k = Laxis/2.
     double kscale;
+    // Four-step passes (an axis of length L_big = L1 * L2 done as length-L1
+    // and length-L2 transforms).  post_tw: stored outputs are multiplied by
+    // W_{L_big}^{o e} (1) or its conjugate (2), o the pencil's outer index and
+    // e the output index.  fs_L1: the spectral index along the axis is
+    // o + fs_L1 * e (0: it is e).
+    const void* tw_big;
+    int L_big;
+    int post_tw;
+    int fs_L1;
 };
 
 // ----------------------------------------------------- plan precompute ----

@@ -18,6 +18,24 @@ int fast_C_512(int mode, bool fp64);
 hipError_t launch_fast_512(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
 int fast_C_1024(int mode, bool fp64);
 hipError_t launch_fast_1024(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
+int fast_C_2048(int mode, bool fp64);
+hipError_t launch_fast_2048(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
+int fast_C_4096(int mode, bool fp64);
+hipError_t launch_fast_4096(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
+int fast_C_8192(int mode, bool fp64);
+hipError_t launch_fast_8192(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
+
+// (declarations of the per-length offset checks)
+bool fast_fits_64(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
+bool fast_fits_96(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
+bool fast_fits_128(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
+bool fast_fits_192(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
+bool fast_fits_256(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
+bool fast_fits_512(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
+bool fast_fits_1024(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
+bool fast_fits_2048(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
+bool fast_fits_4096(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
+bool fast_fits_8192(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
 
 // Pencils per workgroup the specialised kernel uses for (L, mode, precision),
 // or 0 when no specialisation exists (the generic kernel is used).
@@ -30,7 +48,27 @@ int fast_pass_C(int L, int mode, bool fp64) {
         case 256: return fast_C_256(mode, fp64);
         case 512: return fast_C_512(mode, fp64);
         case 1024: return fast_C_1024(mode, fp64);
+        case 2048: return fast_C_2048(mode, fp64);
+        case 4096: return fast_C_4096(mode, fp64);
+        case 8192: return fast_C_8192(mode, fp64);
         default: return 0;
+    }
+}
+
+// Whether the specialised kernel's 32-bit lane offsets cover these strides.
+bool fast_pass_fits(int L, int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq) {
+    switch (L) {
+        case 64: return fast_fits_64(mode, fp64, ise, ose, iiq, oiq);
+        case 96: return fast_fits_96(mode, fp64, ise, ose, iiq, oiq);
+        case 128: return fast_fits_128(mode, fp64, ise, ose, iiq, oiq);
+        case 192: return fast_fits_192(mode, fp64, ise, ose, iiq, oiq);
+        case 256: return fast_fits_256(mode, fp64, ise, ose, iiq, oiq);
+        case 512: return fast_fits_512(mode, fp64, ise, ose, iiq, oiq);
+        case 1024: return fast_fits_1024(mode, fp64, ise, ose, iiq, oiq);
+        case 2048: return fast_fits_2048(mode, fp64, ise, ose, iiq, oiq);
+        case 4096: return fast_fits_4096(mode, fp64, ise, ose, iiq, oiq);
+        case 8192: return fast_fits_8192(mode, fp64, ise, ose, iiq, oiq);
+        default: return false;
     }
 }
 
@@ -43,6 +81,9 @@ hipError_t launch_fast_pass(const PassDesc& p, int mode, int kind, bool fp64, hi
         case 256: return launch_fast_256(p, mode, kind, fp64, s);
         case 512: return launch_fast_512(p, mode, kind, fp64, s);
         case 1024: return launch_fast_1024(p, mode, kind, fp64, s);
+        case 2048: return launch_fast_2048(p, mode, kind, fp64, s);
+        case 4096: return launch_fast_4096(p, mode, kind, fp64, s);
+        case 8192: return launch_fast_8192(p, mode, kind, fp64, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -2,5 +2,5 @@
 #include "fft_fast_impl.h"
 
 namespace vg {
-VG_FAST_INSTANTIATE(128)
+VG_FAST_INSTANTIATE(128, false)
 }  // namespace vg

@@ -2,5 +2,5 @@
 #include "fft_fast_impl.h"
 
 namespace vg {
-VG_FAST_INSTANTIATE(192)
+VG_FAST_INSTANTIATE(192, false)
 }  // namespace vg

@@ -2,5 +2,5 @@
 #include "fft_fast_impl.h"
 
 namespace vg {
-VG_FAST_INSTANTIATE(256)
+VG_FAST_INSTANTIATE(256, false)
 }  // namespace vg

@@ -2,5 +2,5 @@
 #include "fft_fast_impl.h"
 
 namespace vg {
-VG_FAST_INSTANTIATE(512)
+VG_FAST_INSTANTIATE(512, false)
 }  // namespace vg

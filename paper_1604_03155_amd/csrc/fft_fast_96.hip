@@ -2,5 +2,5 @@
 #include "fft_fast_impl.h"
 
 namespace vg {
-VG_FAST_INSTANTIATE(96)
+VG_FAST_INSTANTIATE(96, false)
 }  // namespace vg

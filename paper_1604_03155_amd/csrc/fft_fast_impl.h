@@ -79,16 +79,19 @@ constexpr int ns_before(RP p, int s) {
     return v;
 }
 
-template <int L, int C, int MODE>
+template <int L, int C, int MODE, int ES>
 struct Lay {
     // LDS slot of element e of pencil q.  Column tiles: pencil index fastest
     // (lanes of a wave touch consecutive slots).  Row tiles: element index
-    // fastest, with one padding slot per 16 to break power-of-two strides.
-    static constexpr int LP = L + L / 16;
+    // fastest, with one padding slot per 16 (when it fits in 64 KiB) to break
+    // power-of-two strides.
+    static constexpr bool PAD = MODE == MODE_ROW && C * (L + L / 16) * ES <= 65536;
+    static constexpr int LP = PAD ? L + L / 16 : L;
     static constexpr int size = MODE == MODE_COL ? C * L : C * LP;
     __device__ static __forceinline__ int idx(int q, int e) {
         if constexpr (MODE == MODE_COL) return e * C + q;
-        else return q * LP + e + (e >> 4);
+        else if constexpr (PAD) return q * LP + e + (e >> 4);
+        else return q * LP + e;
     }
 };
 
@@ -148,7 +151,7 @@ __device__ __forceinline__ void compute_stage(cplx<R>* v, int t, const cplx<R>* 
 // outputs of stage s -> LDS, barrier, inputs of stage s+1 <- LDS, barrier
 template <typename R, int L, int C, int NT, int MODE, RP P, int s>
 __device__ __forceinline__ void exchange(cplx<R>* v, cplx<R>* lds, int t) {
-    using LY = Lay<L, C, MODE>;
+    using LY = Lay<L, C, MODE, (int)sizeof(cplx<R>)>;
     constexpr int RAD = P.r[s];
     constexpr int NS = ns_before(P, s);
     constexpr int E = C * L / NT;
@@ -454,7 +457,7 @@ __global__ void __launch_bounds__(NT) fast_kernel(PassDesc p) {
     constexpr bool FL = KindIO<FK>::fwd_load;
     constexpr RP PL = FL ? F : I;
     constexpr int NIN = FL ? L / 2 : L;
-    using LY = Lay<L, C, MODE>;
+    using LY = Lay<L, C, MODE, (int)sizeof(cplx<R>)>;
     __shared__ cplx<R> lds[LY::size];
     const int t = threadIdx.x;
     const FTile tl = fast_tile<C, MODE>(p, xcd_tile(blockIdx.x, gridDim.x));
@@ -482,7 +485,9 @@ hipError_t launch_shape(const PassDesc& p, int kind, hipStream_t s) {
     if (nblocks <= 0) return hipSuccess;
     if (nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     const bool fused = kind == KIND_FUSED || kind == KIND_FUSED_GRAD;
-    if (fused && MODE == MODE_COL) {
+    if constexpr (MODE == MODE_ROW) {
+        if (fused) return hipErrorInvalidValue;  // fused passes are column passes
+    } else if (fused) {
         const bool g = kind == KIND_FUSED_GRAD;
         if (p.d == 3 && p.table_complex)
             return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 3, true>(p, nblocks, s)
@@ -524,25 +529,63 @@ constexpr Shape shape_for(int L, int mode, int esize) {
     const int LP = mode == MODE_COL ? L : L + L / 16;
     int C = mode == MODE_COL ? 16 : 8;
     while (C > 1 && C * LP * esize > 65536) C /= 2;
+    if (C * LP * esize > 65536 && L * esize > 65536) return Shape{0, E, 0};  // one pencil does not fit
     while (C * L / E < 64 && C < 64 && 2 * C * LP * esize <= 65536) C *= 2;
     return Shape{C, E, C * L / E};
 }
 
+// ROWS_ONLY: long lengths are instantiated for row passes only (their column
+// passes use the four-step decomposition).
 template <typename R, int L, int MODE>
 hipError_t launch_len_mode(const PassDesc& p, int kind, hipStream_t s) {
     constexpr Shape S = shape_for(L, MODE, (int)sizeof(cplx<R>));
-    static_assert(S.C * L % S.E == 0 && S.NT >= 64 && S.NT <= 1024, "bad launch shape");
-    if (p.C != S.C) return hipErrorInvalidValue;
-    return launch_shape<R, L, S.C, S.NT, MODE>(p, kind, s);
+    if constexpr (S.C == 0) {
+        return hipErrorInvalidValue;
+    } else {
+        static_assert(S.C * L % S.E == 0 && S.NT >= 64 && S.NT <= 1024, "bad launch shape");
+        if (p.C != S.C) return hipErrorInvalidValue;
+        return launch_shape<R, L, S.C, S.NT, MODE>(p, kind, s);
+    }
 }
 
-template <typename R, int L>
+template <typename R, int L, bool ROWS_ONLY>
 hipError_t launch_len(const PassDesc& p, int mode, int kind, hipStream_t s) {
-    return mode == MODE_COL ? launch_len_mode<R, L, MODE_COL>(p, kind, s) : launch_len_mode<R, L, MODE_ROW>(p, kind, s);
+    if (mode == MODE_ROW) return launch_len_mode<R, L, MODE_ROW>(p, kind, s);
+    if constexpr (ROWS_ONLY) return hipErrorInvalidValue;
+    else return launch_len_mode<R, L, MODE_COL>(p, kind, s);
 }
 
-template <typename R, int L>
+// Whether the 32-bit lane offsets of the specialised kernel cover a pass
+// with these strides (element units): lane part (q iq + j se) * size, with
+// j below L / (radix of the loading or storing stage).
+template <typename R, int L, int MODE>
+bool offsets_fit(long long in_se, long long out_se, long long in_iq, long long out_iq) {
+    constexpr RP F = make_plan(L, kMaxRad<R>);
+    constexpr RP I = reversed(F);
+    constexpr Shape S = shape_for(L, MODE, (int)sizeof(cplx<R>));
+    if constexpr (S.C == 0) {
+        return false;
+    } else {
+        const int rl = F.r[0] < I.r[0] ? F.r[0] : I.r[0];
+        const int rs = F.r[F.n - 1] < I.r[I.n - 1] ? F.r[F.n - 1] : I.r[I.n - 1];
+        const long double es = (long double)sizeof(cplx<R>);
+        const long double lim = 4294967296.0L;
+        const long double a = ((long double)(S.C - 1) * in_iq + (long double)(L / rl - 1) * in_se) * es;
+        const long double b = ((long double)(S.C - 1) * out_iq + (long double)(L / rs - 1) * out_se) * es;
+        return a < lim && b < lim;
+    }
+}
+
+template <typename R, int L, bool ROWS_ONLY>
+bool fits(int mode, long long in_se, long long out_se, long long in_iq, long long out_iq) {
+    if (mode == MODE_ROW) return offsets_fit<R, L, MODE_ROW>(in_se, out_se, in_iq, out_iq);
+    if constexpr (ROWS_ONLY) return false;
+    else return offsets_fit<R, L, MODE_COL>(in_se, out_se, in_iq, out_iq);
+}
+
+template <typename R, int L, bool ROWS_ONLY>
 int shape_C(int mode) {
+    if (mode == MODE_COL && ROWS_ONLY) return 0;
     return mode == MODE_COL ? shape_for(L, MODE_COL, (int)sizeof(cplx<R>)).C
                             : shape_for(L, MODE_ROW, (int)sizeof(cplx<R>)).C;
 }
@@ -551,13 +594,17 @@ int shape_C(int mode) {
 
 // One translation unit per length instantiates these through
 // VG_FAST_INSTANTIATE(L); fft_fast.hip dispatches on the length.
-#define VG_FAST_INSTANTIATE(LL)                                                                         \
-    int fast_C_##LL(int mode, bool fp64) {                                                              \
-        return fp64 ? fastfft::shape_C<double, LL>(mode) : fastfft::shape_C<float, LL>(mode);           \
-    }                                                                                                   \
-    hipError_t launch_fast_##LL(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s) {      \
-        return fp64 ? fastfft::launch_len<double, LL>(p, mode, kind, s)                                 \
-                    : fastfft::launch_len<float, LL>(p, mode, kind, s);                                 \
+#define VG_FAST_INSTANTIATE(LL, ROWS_ONLY)                                                                   \
+    int fast_C_##LL(int mode, bool fp64) {                                                                   \
+        return fp64 ? fastfft::shape_C<double, LL, ROWS_ONLY>(mode) : fastfft::shape_C<float, LL, ROWS_ONLY>(mode); \
+    }                                                                                                        \
+    bool fast_fits_##LL(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq) {  \
+        return fp64 ? fastfft::fits<double, LL, ROWS_ONLY>(mode, ise, ose, iiq, oiq)                          \
+                    : fastfft::fits<float, LL, ROWS_ONLY>(mode, ise, ose, iiq, oiq);                           \
+    }                                                                                                        \
+    hipError_t launch_fast_##LL(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s) {           \
+        return fp64 ? fastfft::launch_len<double, LL, ROWS_ONLY>(p, mode, kind, s)                           \
+                    : fastfft::launch_len<float, LL, ROWS_ONLY>(p, mode, kind, s);                           \
     }
 
 }  // namespace vg

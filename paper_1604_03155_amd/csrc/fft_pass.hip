@@ -31,6 +31,7 @@ struct Tile {
     long long in_qstride, out_qstride;
     int nvalid;                     // pencils of this tile that exist
     int col0;                       // first column (column passes)
+    long long o;                    // outer index (column passes)
 };
 
 template <int MODE>
@@ -51,6 +52,7 @@ __device__ __forceinline__ Tile make_tile(const PassDesc& p) {
         t.out_qstride = 1;
         t.nvalid = min(p.C, p.inner - c0);
         t.col0 = c0;
+        t.o = o;
     } else {
         const long long o0 = (long long)blockIdx.x * p.C;
         t.in_base0 = o0 * p.in_so;
@@ -59,6 +61,7 @@ __device__ __forceinline__ Tile make_tile(const PassDesc& p) {
         t.out_qstride = p.out_so;
         t.nvalid = (int)min((long long)p.C, (long long)p.outer - o0);
         t.col0 = 0;
+        t.o = 0;
     }
     return t;
 }
@@ -69,17 +72,25 @@ __device__ __forceinline__ int signed_freq(int e, int L) {
     return e < h ? e : (e == h && !(L & 1) ? 0 : e - L);
 }
 
+// Length of the whole axis and the spectral index along it of output e of a
+// pencil with outer index o (four-step passes map (o, e) to o + L1 e).
+__device__ __forceinline__ int axis_len(const PassDesc& p) { return p.L_big ? p.L_big : p.L; }
+__device__ __forceinline__ int axis_index(const PassDesc& p, int e, long long o) {
+    return p.fs_L1 ? (int)(o + (long long)p.fs_L1 * e) : e;
+}
+
 template <typename R>
-__device__ __forceinline__ cplx<R> times_ikappa(cplx<R> v, int e, int L, double kscale) {
-    const R kap = R(kscale * (double)signed_freq(e, L));
+__device__ __forceinline__ cplx<R> times_ikappa(cplx<R> v, int k, int L, double kscale) {
+    const R kap = R(kscale * (double)signed_freq(k, L));
     return mk(-kap * v.y, kap * v.x);
 }
 
 template <typename R>
-__device__ __forceinline__ cplx<R> table_value(const PassDesc& p, int e, int col) {
-    const int L = p.L;
+__device__ __forceinline__ cplx<R> table_value(const PassDesc& p, int e, int col, long long o) {
+    const int L = axis_len(p);
+    const int k = axis_index(p, e, o);
     const int N1 = p.tabN + 1;
-    const int f1 = min(e, L - e);
+    const int f1 = min(k, L - k);
     long long flat;
     if (p.d == 3) {
         const int k2 = col / L, k3 = col - (col / L) * L;
@@ -89,6 +100,14 @@ __device__ __forceinline__ cplx<R> table_value(const PassDesc& p, int e, int col
     }
     if (p.table_complex) return reinterpret_cast<const cplx<R>*>(p.table)[flat];
     return mk(reinterpret_cast<const R*>(p.table)[flat], R(0));
+}
+
+// four-step twiddle W_{L_big}^{o e} (post_tw == 1) or its conjugate (2)
+template <typename R>
+__device__ __forceinline__ cplx<R> post_twiddle(const PassDesc& p, cplx<R> v, int e, long long o) {
+    const long long idx = (o * (long long)e) % p.L_big;
+    const cplx<R> w = reinterpret_cast<const cplx<R>*>(p.tw_big)[idx];
+    return p.post_tw == 1 ? cmul(v, w) : cmulc(v, w);
 }
 
 // One run of S Stockham stages.
@@ -138,8 +157,11 @@ __device__ void run_fft(const PassDesc& p, const Tile& t, int src_kind, const cp
                     if (gload) {
                         x = mk(R(0), R(0));
                         if (qok && e < p.n_in) x = gsrc[t.in_base0 + q * t.in_qstride + (long long)e * p.in_se];
-                        if (rawdst) rawdst[lidx<MODE>(q, e, C, L)] = times_ikappa(x, e, L, p.kscale);
-                        if (deriv_in) x = times_ikappa(x, e, L, p.kscale);
+                        if (rawdst || deriv_in) {
+                            const cplx<R> dx = times_ikappa(x, axis_index(p, e, t.o), axis_len(p), p.kscale);
+                            if (rawdst) rawdst[lidx<MODE>(q, e, C, L)] = dx;
+                            if (deriv_in) x = dx;
+                        }
                     } else {
                         x = in_l[lidx<MODE>(q, e, C, L)];
                     }
@@ -163,9 +185,11 @@ __device__ void run_fft(const PassDesc& p, const Tile& t, int src_kind, const cp
                 if (r < Rr) {
                     const int e = ob + r * Ns;
                     if (last && dst_kind == DST_GLOBAL) {
-                        if (qok && e < p.n_out) gdst[t.out_base0 + q * t.out_qstride + (long long)e * p.out_se] = v[r];
+                        if (qok && e < p.n_out)
+                            gdst[t.out_base0 + q * t.out_qstride + (long long)e * p.out_se] =
+                                p.post_tw ? post_twiddle(p, v[r], e, t.o) : v[r];
                     } else if (last && dst_kind == DST_TABLE) {
-                        out_l[lidx<MODE>(q, e, C, L)] = cmul(v[r], table_value<R>(p, e, t.col0 + q));
+                        out_l[lidx<MODE>(q, e, C, L)] = cmul(v[r], table_value<R>(p, e, t.col0 + q, t.o));
                     } else {
                         out_l[lidx<MODE>(q, e, C, L)] = v[r];
                     }
@@ -210,7 +234,7 @@ __global__ void __launch_bounds__(256) fft_pass_kernel(PassDesc p) {
                 e = i % p.L;
                 q = i / p.L;
             }
-            b1[i] = times_ikappa(b2[i], e, p.L, p.kscale);
+            b1[i] = times_ikappa(b2[i], axis_index(p, e, t.o), axis_len(p), p.kscale);
             (void)q;
         }
         __syncthreads();
@@ -287,10 +311,10 @@ int fast_pass_C(int L, int mode, bool fp64);
 hipError_t launch_fast_pass(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
 
 // kind values >= 100 select the derivative-only inverse (kind - 100 ignored).
-// Lengths with a specialised kernel go there when the descriptor's tile width
-// matches its shape; everything else runs the generic kernel.
+// Steps the plan marked specialised run the length-specialised kernels;
+// everything else runs the generic kernel.
 hipError_t launch_fft_pass(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s) {
-    if (p.C > 0 && fast_pass_C(p.L, mode, fp64) == p.C) return launch_fast_pass(p, mode, kind, fp64, s);
+    if (p.specialised) return launch_fast_pass(p, mode, kind, fp64, s);
     const bool deriv_only = kind >= 100;
     if (deriv_only) kind = KIND_INV;
     if (fp64) {

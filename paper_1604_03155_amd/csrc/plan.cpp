@@ -268,8 +268,10 @@ vg_status precompute(vg_plan* p, hipStream_t s, bool keep_T) {
     return VG_OK;
 }
 
-vg_status make_twiddles(vg_plan* p, hipStream_t s) {
-    const int L = 2 * p->N;
+// Twiddle table e^{-2 pi i t / L}, t in [0, L), computed in long double from
+// the exact integer angle and rounded once (cached per length on the plan).
+vg_status twiddle_table(vg_plan* p, int L, hipStream_t s) {
+    if (p->twiddles.count(L)) return VG_OK;
     const size_t esz = p->fp64 ? 16 : 8;
     std::vector<unsigned char> h((size_t)L * esz);
     for (int t = 0; t < L; ++t) {
@@ -284,23 +286,57 @@ vg_status make_twiddles(vg_plan* p, hipStream_t s) {
             q[1] = (float)sn;
         }
     }
-    hipError_t e = dev_malloc(&p->twiddle, h.size());
+    void* d = nullptr;
+    hipError_t e = dev_malloc(&d, h.size());
     if (e != hipSuccess) return from_hip(e, "twiddle allocation");
-    e = hipMemcpyAsync(p->twiddle, h.data(), h.size(), hipMemcpyHostToDevice, s);
+    p->twiddles[L] = d;
+    e = hipMemcpyAsync(d, h.data(), h.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     return from_hip(e, "twiddle upload");
 }
 
+int fast_pass_C(int L, int mode, bool fp64);
+bool fast_pass_fits(int L, int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
+int fft_max_lds_bytes_for_device();
+
 // ------------------------------------------------------------- programs --
 namespace {
 
-PassDesc base_desc(const vg_plan* p) {
+int lds_buffers_generic(int kind) {
+    return (kind == KIND_FUSED || kind == KIND_FUSED_GRAD || kind == KIND_INV_GRAD) ? 3 : 2;
+}
+
+// Tile width of one step: the specialised kernel's when one exists for its
+// length (and the step needs no four-step twiddles), else the generic
+// kernel's, sized so its ping-pong LDS stays within 64 KiB where possible.
+// Returns 0 when not even one pencil fits in LDS.
+int choose_C(const vg_plan* p, const PassStep& st, bool* specialised) {
+    *specialised = false;
+    const PassDesc& d = st.desc;
+    const bool four = d.post_tw != 0 || d.fs_L1 != 0;
+    if (!four && !std::getenv("VG_GENERIC_PASSES")) {
+        const int fc = fast_pass_C(d.L, st.mode, p->fp64);
+        const bool rowm = st.mode == MODE_ROW;
+        if (fc > 0 && fast_pass_fits(d.L, st.mode, p->fp64, d.in_se, d.out_se, rowm ? d.in_so : 1, rowm ? d.out_so : 1)) {
+            *specialised = true;
+            return fc;
+        }
+    }
+    const size_t es = p->fp64 ? 16 : 8;
+    const int nbuf = lds_buffers_generic(st.kind >= 100 ? KIND_INV : st.kind);
+    int c = st.mode == MODE_COL ? 16 : 4;
+    while (c > 1 && (size_t)nbuf * c * d.L * es > 65536) c /= 2;
+    if ((size_t)nbuf * c * d.L * es > (size_t)fft_max_lds_bytes_for_device()) return 0;
+    return c;
+}
+
+PassDesc base_desc(const vg_plan* p, int L) {
     PassDesc d;
     std::memset(&d, 0, sizeof(d));
-    d.L = 2 * p->N;
-    d.nst = (int)p->radices.size();
-    for (int i = 0; i < d.nst; ++i) d.radix[i] = p->radices[i];
-    d.tw = p->twiddle;
+    d.L = L;
+    const std::vector<int> rad = radix_plan(L);
+    d.nst = (int)rad.size();
+    for (int i = 0; i < d.nst; ++i) d.radix[i] = rad[i];
     d.table = p->table;
     d.d = p->d;
     d.tabN = p->N;
@@ -312,7 +348,7 @@ PassDesc base_desc(const vg_plan* p) {
 PassStep row_step(const vg_plan* p, int kind, int in_buf, long long in_pitch, int n_in, int out_buf,
                   long long out_pitch, int n_out, long long rows, const char* name, int out2_buf = BUF_NONE) {
     PassStep s;
-    s.desc = base_desc(p);
+    s.desc = base_desc(p, 2 * p->N);
     s.desc.in_so = in_pitch;
     s.desc.in_se = 1;
     s.desc.out_so = out_pitch;
@@ -321,21 +357,21 @@ PassStep row_step(const vg_plan* p, int kind, int in_buf, long long in_pitch, in
     s.desc.n_out = n_out;
     s.desc.inner = 1;
     s.desc.outer = (int)rows;
-    s.desc.C = p->tc.C_row;
     s.mode = MODE_ROW;
     s.kind = kind;
     s.in_buf = in_buf;
     s.out_buf = out_buf;
     s.out2_buf = out2_buf;
     s.name = name;
+    s.bytes = 0;
     return s;
 }
 
 PassStep col_step(const vg_plan* p, int kind, int in_buf, long long in_so, long long in_se, int n_in, int out_buf,
                   long long out_so, long long out_se, int n_out, long long inner, long long outer, const char* name,
-                  int out2_buf = BUF_NONE) {
+                  int out2_buf = BUF_NONE, int L = 0) {
     PassStep s;
-    s.desc = base_desc(p);
+    s.desc = base_desc(p, L ? L : 2 * p->N);
     s.desc.in_so = in_so;
     s.desc.in_se = in_se;
     s.desc.out_so = out_so;
@@ -344,13 +380,13 @@ PassStep col_step(const vg_plan* p, int kind, int in_buf, long long in_so, long 
     s.desc.n_out = n_out;
     s.desc.inner = (int)inner;
     s.desc.outer = (int)outer;
-    s.desc.C = (kind == KIND_FUSED || kind == KIND_FUSED_GRAD) ? p->tc.C_fused : p->tc.C_col;
     s.mode = MODE_COL;
     s.kind = kind;
     s.in_buf = in_buf;
     s.out_buf = out_buf;
     s.out2_buf = out2_buf;
     s.name = name;
+    s.bytes = 0;
     return s;
 }
 
@@ -364,6 +400,25 @@ void set_ws(Program& prog, const std::vector<size_t>& sizes_bytes) {
     prog.ws_bytes = off;
 }
 
+// Four-step split L = L1 * L2 of a long column axis: L1 even (the zero padding
+// of the first step is then its upper half), both factors as close to sqrt(L)
+// as possible.  0 if none exists.
+int four_step_L1(int L) {
+    int best = 0;
+    double bestd = 1e30;
+    for (int a = 2; a < L; a += 2) {
+        if (L % a) continue;
+        const int b = L / a;
+        if (radix_plan(a).empty() || radix_plan(b).empty()) continue;
+        const double dd = std::fabs(std::log((double)a) - std::log((double)b));
+        if (dd < bestd - 1e-12) {
+            bestd = dd;
+            best = a;
+        }
+    }
+    return best;
+}
+
 }  // namespace
 
 void finalize_bytes(vg_plan* p);
@@ -371,7 +426,16 @@ void finalize_bytes(vg_plan* p);
 // Intermediate layouts.  A column tile whose rows are a large power of two
 // apart (a whole 2N x 2N plane in 3D, a 2N row in 2D) keeps hitting the same
 // HBM channels, so those pitches are lengthened by 256 bytes.
-void build_programs(vg_plan* p) {
+//
+// A 2D column axis too long for one LDS-resident pencil runs as four steps
+// (L = L1 L2, n = L2 n1 + n2, k = k1 + L1 k2):
+//   A : for each n2, length-L1 forward DFT over n1 (upper half zero), times
+//       W_L^{n2 k1}, stored back at row L2 k1 + n2;
+//   B : for each k1, length-L2 forward DFT over n2 -> spectral index
+//       k1 + L1 k2, times Khat (and i kappa), length-L2 inverse, times
+//       W_L^{-n2 k1}, stored back in place;
+//   A': for each n2, length-L1 inverse over k1, rows with n1 < L1/2 kept.
+vg_status build_programs(vg_plan* p, hipStream_t stream) {
     const long long N = p->N, L = 2 * N;
     const size_t es = p->fp64 ? 16 : 8;
     const long long PAD = 256 / (long long)es;
@@ -381,7 +445,6 @@ void build_programs(vg_plan* p) {
     A.steps.clear();
     G.steps.clear();
     if (p->d == 3) {
-        const long long V = N * N * N;
         const long long PL = L * L + PAD;   // plane pitch of the [N][L][L] intermediates
         const long long PS = N * L;         // [N][N][L] intermediates stay dense (pencil stride L)
         const size_t b2 = (size_t)(N * PS) * es, b4 = (size_t)(N * PL) * es;
@@ -407,22 +470,82 @@ void build_programs(vg_plan* p) {
                                    BUF_GRAD0 + 2));
         G.steps.push_back(row_step(p, KIND_INV, W3, L, (int)L, BUF_GRAD0 + 1, N, (int)N, N * N, "g5_row_inv_d2"));
         G.steps.push_back(row_step(p, KIND_INV, W4, L, (int)L, BUF_GRAD0 + 0, N, (int)N, N * N, "g5_row_inv_d1"));
-        (void)V;
     } else {
-        const long long RP = L + PAD;  // row pitch of the [N][L] intermediates
-        const size_t b2 = (size_t)(N * RP) * es;
-        set_ws(A, {b2});
-        A.steps.push_back(row_step(p, KIND_FWD, BUF_F, N, (int)N, W0, RP, (int)L, N, "p1_row_fwd"));
-        A.steps.push_back(col_step(p, KIND_FUSED, W0, 0, RP, (int)N, W0, 0, RP, (int)N, L, 1, "p2_fused"));
-        A.steps.push_back(row_step(p, KIND_INV, W0, RP, (int)L, BUF_PHI, N, (int)N, N, "p3_row_inv"));
-        set_ws(G, {b2, b2});
-        G.steps.push_back(row_step(p, KIND_FWD, BUF_F, N, (int)N, W0, RP, (int)L, N, "g1_row_fwd"));
-        G.steps.push_back(col_step(p, KIND_FUSED_GRAD, W0, 0, RP, (int)N, W0, 0, RP, (int)N, L, 1, "g2_fused_grad", W1));
-        G.steps.push_back(row_step(p, KIND_INV_GRAD, W0, RP, (int)L, BUF_PHI, N, (int)N, N, "g3_row_inv_grad",
-                                   BUF_GRAD0 + 1));
-        G.steps.push_back(row_step(p, KIND_INV, W1, RP, (int)L, BUF_GRAD0 + 0, N, (int)N, N, "g3_row_inv_d1"));
+        const long long RP = L + PAD;  // row pitch of the [rows][L] intermediates
+        PassStep fused = col_step(p, KIND_FUSED, W0, 0, RP, (int)N, W0, 0, RP, (int)N, L, 1, "p2_fused");
+        bool spec = false;
+        const bool single = choose_C(p, fused, &spec) > 0 && (spec || L <= 1024);
+        if (single) {
+            const size_t b2 = (size_t)(N * RP) * es;
+            set_ws(A, {b2});
+            A.steps.push_back(row_step(p, KIND_FWD, BUF_F, N, (int)N, W0, RP, (int)L, N, "p1_row_fwd"));
+            A.steps.push_back(fused);
+            A.steps.push_back(row_step(p, KIND_INV, W0, RP, (int)L, BUF_PHI, N, (int)N, N, "p3_row_inv"));
+            set_ws(G, {b2, b2});
+            G.steps.push_back(row_step(p, KIND_FWD, BUF_F, N, (int)N, W0, RP, (int)L, N, "g1_row_fwd"));
+            G.steps.push_back(col_step(p, KIND_FUSED_GRAD, W0, 0, RP, (int)N, W0, 0, RP, (int)N, L, 1,
+                                       "g2_fused_grad", W1));
+            G.steps.push_back(row_step(p, KIND_INV_GRAD, W0, RP, (int)L, BUF_PHI, N, (int)N, N, "g3_row_inv_grad",
+                                       BUF_GRAD0 + 1));
+            G.steps.push_back(row_step(p, KIND_INV, W1, RP, (int)L, BUF_GRAD0 + 0, N, (int)N, N, "g3_row_inv_d1"));
+        } else {
+            const int L1 = four_step_L1((int)L);
+            if (L1 == 0) return fail(VG_ERR_UNSUPPORTED_SIZE, "no four-step split of 2N");
+            const int L2 = (int)(L / L1);
+            const size_t bL = (size_t)(L * RP) * es;  // all L rows carry data between the steps
+            auto stepA = [&](int kind, int buf, const char* name) {
+                // outer n2 (row offset RP), columns (inner L), elements n1 (stride L2 rows)
+                PassStep s = col_step(p, kind, buf, RP, (long long)L2 * RP, kind == KIND_FWD ? L1 / 2 : L1, buf, RP,
+                                      (long long)L2 * RP, kind == KIND_FWD ? L1 : L1 / 2, L, L2, name, BUF_NONE, L1);
+                s.desc.L_big = (int)L;
+                s.desc.post_tw = kind == KIND_FWD ? 1 : 0;
+                return s;
+            };
+            auto stepB = [&](int kind, int buf, int buf2, const char* name) {
+                // outer k1 (offset L2 rows), columns, elements n2 (stride one row)
+                PassStep s = col_step(p, kind, buf, (long long)L2 * RP, RP, L2, buf, (long long)L2 * RP, RP, L2, L, L1,
+                                      name, buf2, L2);
+                s.desc.L_big = (int)L;
+                s.desc.post_tw = 2;
+                s.desc.fs_L1 = L1;
+                return s;
+            };
+            set_ws(A, {bL});
+            A.steps.push_back(row_step(p, KIND_FWD, BUF_F, N, (int)N, W0, RP, (int)L, N, "p1_row_fwd"));
+            A.steps.push_back(stepA(KIND_FWD, W0, "p2a_col_fwd"));
+            A.steps.push_back(stepB(KIND_FUSED, W0, BUF_NONE, "p2b_fused"));
+            A.steps.push_back(stepA(KIND_INV, W0, "p2c_col_inv"));
+            A.steps.push_back(row_step(p, KIND_INV, W0, RP, (int)L, BUF_PHI, N, (int)N, N, "p3_row_inv"));
+            set_ws(G, {bL, bL});
+            G.steps.push_back(row_step(p, KIND_FWD, BUF_F, N, (int)N, W0, RP, (int)L, N, "g1_row_fwd"));
+            G.steps.push_back(stepA(KIND_FWD, W0, "g2a_col_fwd"));
+            G.steps.push_back(stepB(KIND_FUSED_GRAD, W0, W1, "g2b_fused_grad"));
+            G.steps.push_back(stepA(KIND_INV, W0, "g2c_col_inv"));
+            G.steps.push_back(stepA(KIND_INV, W1, "g2c_col_inv_d1"));
+            G.steps.push_back(row_step(p, KIND_INV_GRAD, W0, RP, (int)L, BUF_PHI, N, (int)N, N, "g3_row_inv_grad",
+                                       BUF_GRAD0 + 1));
+            G.steps.push_back(row_step(p, KIND_INV, W1, RP, (int)L, BUF_GRAD0 + 0, N, (int)N, N, "g3_row_inv_d1"));
+        }
+    }
+    // twiddles, tile widths and support check for every step
+    for (Program* pr : {&A, &G}) {
+        for (PassStep& st : pr->steps) {
+            vg_status s2 = twiddle_table(p, st.desc.L, stream);
+            if (s2 != VG_OK) return s2;
+            st.desc.tw = p->twiddles[st.desc.L];
+            if (st.desc.L_big) {
+                s2 = twiddle_table(p, st.desc.L_big, stream);
+                if (s2 != VG_OK) return s2;
+                st.desc.tw_big = p->twiddles[st.desc.L_big];
+            }
+            bool spec = false;
+            st.desc.C = choose_C(p, st, &spec);
+            st.desc.specialised = spec ? 1 : 0;
+            if (st.desc.C == 0) return fail(VG_ERR_UNSUPPORTED_SIZE, std::string("pass ") + st.name + ": pencil does not fit in LDS");
+        }
     }
     finalize_bytes(p);
+    return VG_OK;
 }
 
 namespace {
@@ -461,6 +584,7 @@ vg_status run_program(const vg_plan* p, const Program& prog, const void* f, void
     void* mark = profiler_mark(stream);
     for (const PassStep& st : prog.steps) {
         PassDesc d = st.desc;
+        d.table = p->table;  // programs are built before the precompute fills the table
         d.in = resolve(st.in_buf);
         d.out = resolve(st.out_buf);
         d.out2 = resolve(st.out2_buf);
@@ -482,30 +606,5 @@ vg_status run_program(const vg_plan* p, const Program& prog, const void* f, void
     return VG_OK;
 }
 
-int fast_pass_C(int L, int mode, bool fp64);
-
-vg_status autotune(vg_plan* p) {
-    // Lengths with a specialised kernel use its tile width; otherwise the
-    // generic kernel's pencils per workgroup are sized so its ping-pong LDS
-    // stays within 64 KiB where possible.
-    const int L = 2 * p->N;
-    const int fc = fast_pass_C(L, MODE_COL, p->fp64), fr = fast_pass_C(L, MODE_ROW, p->fp64);
-    if (fc > 0 && fr > 0 && !std::getenv("VG_GENERIC_PASSES")) {
-        p->tc.C_col = fc;
-        p->tc.C_fused = fc;
-        p->tc.C_row = fr;
-        return VG_OK;
-    }
-    const size_t es = p->fp64 ? 16 : 8;
-    auto pick = [&](int nbuf, int cmax) {
-        int c = cmax;
-        while (c > 1 && (size_t)nbuf * c * L * es > 65536) c /= 2;
-        return c;
-    };
-    p->tc.C_col = pick(3, 16);
-    p->tc.C_fused = pick(3, 16);
-    p->tc.C_row = pick(3, 4);
-    return VG_OK;
-}
 
 }  // namespace vg

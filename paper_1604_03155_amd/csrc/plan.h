@@ -1,6 +1,7 @@
 // Host-side plan object of the volume-potential library (internal).
 #pragma once
 
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -35,10 +36,6 @@ struct Program {
     size_t ws_bytes = 0;
 };
 
-// Launch shape chosen for each pass role (pencils per workgroup).
-struct TuneChoice {
-    int C_row = 0, C_col = 0, C_fused = 0;
-};
 
 }  // namespace vg
 
@@ -48,13 +45,12 @@ struct vg_plan {
     int device = 0;
     bool fp64 = false;
     std::vector<int> radices;     // Stockham radix plan of length 2N
-    void* twiddle = nullptr;      // device, 2N complex (float or double)
+    std::map<int, void*> twiddles; // device twiddle tables e^{-2 pi i t / L} per length L
     void* table = nullptr;        // device, (N+1)^d Khat octant / (2N)^d
     size_t table_bytes = 0;
     int table_complex = 0;
     void* T_dev = nullptr;        // device, N^d complex128 (keep_operator)
     double precompute_ms = 0.0;
-    vg::TuneChoice tc;
     vg::Program apply_prog, grad_prog;
     // internal workspace for calls with workspace == NULL
     mutable std::mutex ws_mutex;
@@ -72,15 +68,14 @@ vg_status from_hip(hipError_t e, const char* what);
 // another prime factor.
 std::vector<int> radix_plan(int L);
 
-// Build the apply / gradient programs for a plan (after tuning choices).
-void build_programs(vg_plan* p);
+// Build the apply / gradient programs for a plan (allocates the twiddle
+// tables they need); VG_ERR_UNSUPPORTED_SIZE if some pass cannot run.
+vg_status build_programs(vg_plan* p, hipStream_t s);
 
 // Run a program: bind buffers and launch every step on `stream`.
 vg_status run_program(const vg_plan* p, const Program& prog, const void* f, void* phi, void* grad,
                       void* ws, hipStream_t stream);
 
-// Plan-time autotuning of pencils per workgroup.
-vg_status autotune(vg_plan* p);
 
 // Pass profiler hooks (profiler.cpp).
 bool profiler_enabled();
