@@ -136,6 +136,16 @@ __device__ __forceinline__ c64 g_eval(double s, const GreensParams& g) {
 // indices (I == 1), m = last index.
 constexpr int TR = 64, TN = 64, TK = 16;
 
+// s + c += v with the rounding error of the addition carried in c (Knuth's
+// TwoSum).
+__device__ __forceinline__ void two_sum_acc(double& s, double& c, double v) {
+    const double t = s + v;
+    const double bp = t - s;
+    const double err = (s - (t - bp)) + (v - bp);
+    s = t;
+    c += err;
+}
+
 template <bool GEN>
 __global__ void __launch_bounds__(256) contract_kernel(const c64* __restrict__ X, c64* __restrict__ Y,
                                                        const double* __restrict__ Cm, long long rows, int K,
@@ -146,11 +156,14 @@ __global__ void __launch_bounds__(256) contract_kernel(const c64* __restrict__ X
     const int tx = tid % 16, ty = tid / 16;
     const long long r0 = (long long)blockIdx.x * TR;
     const int n0 = blockIdx.y * TN;
-    c64 acc[4][4];
+    c64 acc[4][4], comp[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = mk(0.0, 0.0);
+        for (int b = 0; b < 4; ++b) {
+            acc[a][b] = mk(0.0, 0.0);
+            comp[a][b] = mk(0.0, 0.0);
+        }
 
     for (int m0 = 0; m0 < K; m0 += TK) {
         // stage X tile (TR rows x TK m)
@@ -190,6 +203,14 @@ __global__ void __launch_bounds__(256) contract_kernel(const c64* __restrict__ X
             cs[mm][nn] = (m < K && n < Nout) ? Cm[(long long)n * K + m] : 0.0;
         }
         __syncthreads();
+        // the chunk's TK terms are summed on their own, then added to the
+        // running sums with compensation (TwoSum), so rounding grows with
+        // TK + K/TK terms instead of K
+        c64 part[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) part[a][b] = mk(0.0, 0.0);
 #pragma unroll 4
         for (int mm = 0; mm < TK; ++mm) {
             c64 xv[4];
@@ -202,10 +223,17 @@ __global__ void __launch_bounds__(256) contract_kernel(const c64* __restrict__ X
             for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
-                    acc[a][b].x = fma(xv[a].x, cv[b], acc[a][b].x);
-                    acc[a][b].y = fma(xv[a].y, cv[b], acc[a][b].y);
+                    part[a][b].x = fma(xv[a].x, cv[b], part[a][b].x);
+                    part[a][b].y = fma(xv[a].y, cv[b], part[a][b].y);
                 }
         }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                two_sum_acc(acc[a][b].x, comp[a][b].x, part[a][b].x);
+                two_sum_acc(acc[a][b].y, comp[a][b].y, part[a][b].y);
+            }
         __syncthreads();
     }
 #pragma unroll
@@ -216,7 +244,7 @@ __global__ void __launch_bounds__(256) contract_kernel(const c64* __restrict__ X
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int n = n0 + tx * 4 + b;
-            if (n < Nout) Y[(o * Nout + n) * I + i] = acc[a][b];
+            if (n < Nout) Y[(o * Nout + n) * I + i] = mk(acc[a][b].x + comp[a][b].x, acc[a][b].y + comp[a][b].y);
         }
     }
 }
