@@ -4,6 +4,8 @@
 
 namespace vg {
 
+int fast_C_32(int mode, bool fp64);
+hipError_t launch_fast_32(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
 int fast_C_64(int mode, bool fp64);
 hipError_t launch_fast_64(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
 int fast_C_96(int mode, bool fp64);
@@ -26,6 +28,7 @@ int fast_C_8192(int mode, bool fp64);
 hipError_t launch_fast_8192(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
 
 // (declarations of the per-length offset checks)
+bool fast_fits_32(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
 bool fast_fits_64(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
 bool fast_fits_96(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
 bool fast_fits_128(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
@@ -41,6 +44,7 @@ bool fast_fits_8192(int mode, bool fp64, long long ise, long long ose, long long
 // or 0 when no specialisation exists (the generic kernel is used).
 int fast_pass_C(int L, int mode, bool fp64) {
     switch (L) {
+        case 32: return fast_C_32(mode, fp64);
         case 64: return fast_C_64(mode, fp64);
         case 96: return fast_C_96(mode, fp64);
         case 128: return fast_C_128(mode, fp64);
@@ -58,6 +62,7 @@ int fast_pass_C(int L, int mode, bool fp64) {
 // Whether the specialised kernel's 32-bit lane offsets cover these strides.
 bool fast_pass_fits(int L, int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq) {
     switch (L) {
+        case 32: return fast_fits_32(mode, fp64, ise, ose, iiq, oiq);
         case 64: return fast_fits_64(mode, fp64, ise, ose, iiq, oiq);
         case 96: return fast_fits_96(mode, fp64, ise, ose, iiq, oiq);
         case 128: return fast_fits_128(mode, fp64, ise, ose, iiq, oiq);
@@ -74,6 +79,7 @@ bool fast_pass_fits(int L, int mode, bool fp64, long long ise, long long ose, lo
 
 hipError_t launch_fast_pass(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s) {
     switch (p.L) {
+        case 32: return launch_fast_32(p, mode, kind, fp64, s);
         case 64: return launch_fast_64(p, mode, kind, fp64, s);
         case 96: return launch_fast_96(p, mode, kind, fp64, s);
         case 128: return launch_fast_128(p, mode, kind, fp64, s);

@@ -1,0 +1,6 @@
+// Specialised FFT passes of length 32 (see fft_fast_impl.h).
+#include "fft_fast_impl.h"
+
+namespace vg {
+VG_FAST_INSTANTIATE(32, false)
+}  // namespace vg

@@ -190,6 +190,7 @@ struct FTile {
     long long iq, oq;       // pencil stride
     int nvalid;
     int col0;
+    int o;                  // outer index (column tiles)
 };
 
 // XCD-aware order for one-tile-per-workgroup launches: dispatch slot b runs
@@ -211,6 +212,7 @@ __device__ __forceinline__ FTile fast_tile(const PassDesc& p, unsigned b) {
         t.oq = 1;
         t.nvalid = min(C, p.inner - c0);
         t.col0 = c0;
+        t.o = (int)o;
     } else {
         const long long o0 = (long long)b * C;
         t.in0 = o0 * p.in_so;
@@ -219,6 +221,7 @@ __device__ __forceinline__ FTile fast_tile(const PassDesc& p, unsigned b) {
         t.oq = p.out_so;
         t.nvalid = (int)min((long long)C, (long long)p.outer - o0);
         t.col0 = 0;
+        t.o = 0;
     }
     return t;
 }
@@ -289,9 +292,11 @@ __device__ __forceinline__ void expand(cplx<R>* v, const cplx<R>* vn) {
 
 // registers (outputs of the last stage of plan P) -> global, e < NOUT only.
 // Outputs never stored are dead, so their arithmetic is dropped by the compiler.
-template <typename R, int L, int C, int NT, int MODE, RP P, int NOUT, bool FULL>
+// PT (four-step passes): multiply output e by W_{L_big}^{o e} (1) or its
+// conjugate (2) from the table tw_big, o the tile's outer index.
+template <typename R, int L, int C, int NT, int MODE, RP P, int NOUT, bool FULL, int PT>
 __device__ __forceinline__ void store_global_t(const cplx<R>* v, cplx<R>* __restrict__ g, const FTile& tl,
-                                               long long se, int t) {
+                                               long long se, int t, const void* __restrict__ twb) {
     constexpr int RAD = P.r[P.n - 1];
     constexpr int E = C * L / NT;
     constexpr int LR = L / RAD;
@@ -311,17 +316,23 @@ __device__ __forceinline__ void store_global_t(const cplx<R>* v, cplx<R>* __rest
         if (r * LR < NOUT) {
             cplx<R>* gb = g + tl.out0 + (long long)(r * LR) * se;
 #pragma unroll
-            for (int i = 0; i < E / RAD; ++i)
-                if (ok[i] && ((r + 1) * LR <= NOUT || jj[i] + r * LR < NOUT)) st_off(gb, off[i], v[i * RAD + r]);
+            for (int i = 0; i < E / RAD; ++i) {
+                cplx<R> x = v[i * RAD + r];
+                if constexpr (PT != 0) {
+                    const cplx<R> w = ld_off<cplx<R>>(twb, (unsigned)(tl.o * (jj[i] + r * LR)) * (unsigned)sizeof(cplx<R>));
+                    x = PT == 1 ? cmul(x, w) : cmulc(x, w);
+                }
+                if (ok[i] && ((r + 1) * LR <= NOUT || jj[i] + r * LR < NOUT)) st_off(gb, off[i], x);
+            }
         }
     }
 }
 
-template <typename R, int L, int C, int NT, int MODE, RP P, int NOUT>
+template <typename R, int L, int C, int NT, int MODE, RP P, int NOUT, int PT = 0>
 __device__ __forceinline__ void store_global(const cplx<R>* v, cplx<R>* __restrict__ g, const FTile& tl,
-                                             long long se, int t) {
-    if (tl.nvalid == C) store_global_t<R, L, C, NT, MODE, P, NOUT, true>(v, g, tl, se, t);
-    else store_global_t<R, L, C, NT, MODE, P, NOUT, false>(v, g, tl, se, t);
+                                             long long se, int t, const void* twb = nullptr) {
+    if (tl.nvalid == C) store_global_t<R, L, C, NT, MODE, P, NOUT, true, PT>(v, g, tl, se, t, twb);
+    else store_global_t<R, L, C, NT, MODE, P, NOUT, false, PT>(v, g, tl, se, t, twb);
 }
 
 // Khat octant values for the thread's spectral positions (last-stage outputs
@@ -366,6 +377,33 @@ __device__ __forceinline__ void table_fetch(cplx<R>* kt, const void* __restrict_
     }
 }
 
+// Four-step step B (2D): the spectral index along the axis is k = o + L1 e over
+// the whole axis length Lb; the column index folds over Lb as well.
+template <typename R, int L, int C, int NT, int MODE, RP P, bool CPLX>
+__device__ __forceinline__ void table_fetch_fs(cplx<R>* kt, const void* __restrict__ table, int tabN, int col0,
+                                               int nvalid, int o, int L1, int Lb, int t) {
+    constexpr int RAD = P.r[P.n - 1];
+    constexpr int E = C * L / NT;
+    const int N1 = tabN + 1;
+#pragma unroll
+    for (int i = 0; i < E / RAD; ++i) {
+        int q, j;
+        bmap<L, C, NT, MODE, RAD>(t, i, q, j);
+        const int col = min(col0 + q, col0 + nvalid - 1);
+        const unsigned rowoff = (unsigned)min(col, Lb - col);
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) {
+            const int k = o + L1 * (j + r * (L / RAD));
+            const unsigned flat = (unsigned)min(k, Lb - k) * (unsigned)N1 + rowoff;
+            if constexpr (CPLX) {
+                kt[i * RAD + r] = ld_off<cplx<R>>(table, flat * (unsigned)sizeof(cplx<R>));
+            } else {
+                kt[i * RAD + r] = mk(ld_off<R>(table, flat * (unsigned)sizeof(R)), R(0));
+            }
+        }
+    }
+}
+
 template <typename R, int E, bool CPLX>
 __device__ __forceinline__ void table_apply(cplx<R>* v, const cplx<R>* kt) {
 #pragma unroll
@@ -377,15 +415,20 @@ __device__ __forceinline__ void table_apply(cplx<R>* v, const cplx<R>* kt) {
 
 // v2 = i*kappa(e) * v at the stage-0 input positions (plan P) or last-stage
 // output positions (LAST) -- both are e = j + r L/R.
+// (four-step step B: the spectral index is o + L1 e over the axis length Lb)
 template <typename R, int L, int C, int NT, int MODE, int RAD>
-__device__ __forceinline__ void deriv_copy(const cplx<R>* v, cplx<R>* v2, R ks, int t) {
+__device__ __forceinline__ void deriv_copy(const cplx<R>* v, cplx<R>* v2, R ks, int t, int o = 0, int L1 = 0,
+                                           int Lb = 0) {
     constexpr int E = C * L / NT;
 #pragma unroll
     for (int i = 0; i < E / RAD; ++i) {
         int q, j;
         bmap<L, C, NT, MODE, RAD>(t, i, q, j);
 #pragma unroll
-        for (int r = 0; r < RAD; ++r) v2[i * RAD + r] = ikap(v[i * RAD + r], j + r * (L / RAD), L, ks);
+        for (int r = 0; r < RAD; ++r) {
+            const int e = j + r * (L / RAD);
+            v2[i * RAD + r] = L1 ? ikap(v[i * RAD + r], o + L1 * e, Lb, ks) : ikap(v[i * RAD + r], e, L, ks);
+        }
     }
 }
 
@@ -400,9 +443,14 @@ struct KindIO {
 
 // Everything after the stage-0 loads of one tile: transforms, multiplies,
 // stores.  v holds the stage-0 inputs; kt the Khat values (fused kinds).
-template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX>
+// FS: 0 plain pass; 1 four-step step A (forward, outputs times W^{o e});
+// 2 four-step step B (full-length forward, Khat at index o + L1 e, full-length
+// inverse, outputs times conj W^{o e}).
+template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX, int FS>
 __device__ __forceinline__ void tile_body(cplx<R>* v, cplx<R>* kt, cplx<R>* lds, const FTile& tl,
                                           const PassDesc& p, int t) {
+    constexpr int NOUTI = FS == 2 ? L : L / 2;  // inverse outputs kept
+    constexpr int PTI = FS == 2 ? 2 : 0;        // post twiddle of inverse outputs
     constexpr RP F = make_plan(L, kMaxRad<R>);
     constexpr RP I = reversed(F);
     constexpr int E = C * L / NT;
@@ -412,7 +460,7 @@ __device__ __forceinline__ void tile_body(cplx<R>* v, cplx<R>* kt, cplx<R>* lds,
     const R ks = (R)p.kscale;
     if constexpr (FK == FK_FWD) {
         run_from<R, L, C, NT, MODE, -1, F, 0>(v, lds, t, tw);
-        store_global<R, L, C, NT, MODE, F, L>(v, gout, tl, p.out_se, t);
+        store_global<R, L, C, NT, MODE, F, L, FS == 1 ? 1 : 0>(v, gout, tl, p.out_se, t, p.tw_big);
     } else if constexpr (FK == FK_INV || FK == FK_INV_DERIV) {
         if constexpr (FK == FK_INV_DERIV) {
             cplx<R> w[E];
@@ -435,28 +483,29 @@ __device__ __forceinline__ void tile_body(cplx<R>* v, cplx<R>* kt, cplx<R>* lds,
         table_apply<R, E, CPLX>(v, kt);
         if constexpr (FK == FK_FUSED) {
             run_from<R, L, C, NT, MODE, +1, I, 0>(v, lds, t, tw);
-            store_global<R, L, C, NT, MODE, I, L / 2>(v, gout, tl, p.out_se, t);
+            store_global<R, L, C, NT, MODE, I, NOUTI, PTI>(v, gout, tl, p.out_se, t, p.tw_big);
         } else {
             cplx<R> w[E];
-            deriv_copy<R, L, C, NT, MODE, F.r[F.n - 1]>(v, w, ks, t);
+            if constexpr (FS == 2) deriv_copy<R, L, C, NT, MODE, F.r[F.n - 1]>(v, w, ks, t, tl.o, p.fs_L1, p.L_big);
+            else deriv_copy<R, L, C, NT, MODE, F.r[F.n - 1]>(v, w, ks, t);
             run_from<R, L, C, NT, MODE, +1, I, 0>(v, lds, t, tw);
-            store_global<R, L, C, NT, MODE, I, L / 2>(v, gout, tl, p.out_se, t);
+            store_global<R, L, C, NT, MODE, I, NOUTI, PTI>(v, gout, tl, p.out_se, t, p.tw_big);
             __syncthreads();
             run_from<R, L, C, NT, MODE, +1, I, 0>(w, lds, t, tw);
-            store_global<R, L, C, NT, MODE, I, L / 2>(w, gout2, tl, p.out_se, t);
+            store_global<R, L, C, NT, MODE, I, NOUTI, PTI>(w, gout2, tl, p.out_se, t, p.tw_big);
         }
     }
 }
 
 // One tile per workgroup.
-template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX>
+template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX, int FS>
 __global__ void __launch_bounds__(NT) fast_kernel(PassDesc p) {
     constexpr RP F = make_plan(L, kMaxRad<R>);
     constexpr RP I = reversed(F);
     constexpr int E = C * L / NT;
     constexpr bool FL = KindIO<FK>::fwd_load;
     constexpr RP PL = FL ? F : I;
-    constexpr int NIN = FL ? L / 2 : L;
+    constexpr int NIN = (FL && FS != 2) ? L / 2 : L;
     using LY = Lay<L, C, MODE, (int)sizeof(cplx<R>)>;
     __shared__ cplx<R> lds[LY::size];
     const int t = threadIdx.x;
@@ -466,16 +515,18 @@ __global__ void __launch_bounds__(NT) fast_kernel(PassDesc p) {
     cplx<R> v[E];
     cplx<R> kt[(FK == FK_FUSED || FK == FK_FUSED_GRAD) ? E : 1];
     issue_loads<R, L, C, NT, MODE, PL, NIN>(vn, gin, tl, p.in_se, t);
-    if constexpr (FK == FK_FUSED || FK == FK_FUSED_GRAD)
+    if constexpr ((FK == FK_FUSED || FK == FK_FUSED_GRAD) && FS == 2)
+        table_fetch_fs<R, L, C, NT, MODE, F, CPLX>(kt, p.table, p.tabN, tl.col0, tl.nvalid, tl.o, p.fs_L1, p.L_big, t);
+    else if constexpr (FK == FK_FUSED || FK == FK_FUSED_GRAD)
         table_fetch<R, L, C, NT, MODE, F, D, CPLX>(kt, p.table, p.tabN, tl.col0, tl.nvalid, t);
     expand<R, L, C, NT, PL, NIN>(v, vn);
-    tile_body<R, L, C, NT, MODE, FK, D, CPLX>(v, kt, lds, tl, p, t);
+    tile_body<R, L, C, NT, MODE, FK, D, CPLX, FS>(v, kt, lds, tl, p, t);
 }
 
 // --------------------------------------------------------------- dispatch --
-template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX>
+template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX, int FS = 0>
 hipError_t launch_k(const PassDesc& p, long long ntiles, hipStream_t s) {
-    hipLaunchKernelGGL((fast_kernel<R, L, C, NT, MODE, FK, D, CPLX>), dim3((unsigned)ntiles), dim3(NT), 0, s, p);
+    hipLaunchKernelGGL((fast_kernel<R, L, C, NT, MODE, FK, D, CPLX, FS>), dim3((unsigned)ntiles), dim3(NT), 0, s, p);
     return hipGetLastError();
 }
 
@@ -487,6 +538,15 @@ hipError_t launch_shape(const PassDesc& p, int kind, hipStream_t s) {
     const bool fused = kind == KIND_FUSED || kind == KIND_FUSED_GRAD;
     if constexpr (MODE == MODE_ROW) {
         if (fused) return hipErrorInvalidValue;  // fused passes are column passes
+    } else if (fused && p.fs_L1) {
+        // four-step step B (2D only)
+        const bool g = kind == KIND_FUSED_GRAD;
+        if (p.d != 2 || p.post_tw != 2) return hipErrorInvalidValue;
+        if (p.table_complex)
+            return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 2, true, 2>(p, nblocks, s)
+                     : launch_k<R, L, C, NT, MODE, FK_FUSED, 2, true, 2>(p, nblocks, s);
+        return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 2, false, 2>(p, nblocks, s)
+                 : launch_k<R, L, C, NT, MODE, FK_FUSED, 2, false, 2>(p, nblocks, s);
     } else if (fused) {
         const bool g = kind == KIND_FUSED_GRAD;
         if (p.d == 3 && p.table_complex)
@@ -500,6 +560,14 @@ hipError_t launch_shape(const PassDesc& p, int kind, hipStream_t s) {
                      : launch_k<R, L, C, NT, MODE, FK_FUSED, 2, true>(p, nblocks, s);
         return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 2, false>(p, nblocks, s)
                  : launch_k<R, L, C, NT, MODE, FK_FUSED, 2, false>(p, nblocks, s);
+    }
+    if (p.post_tw || p.fs_L1) {
+        // four-step step A (column forward with post twiddle)
+        if constexpr (MODE == MODE_COL) {
+            if (kind == KIND_FWD && p.post_tw == 1 && !p.fs_L1)
+                return launch_k<R, L, C, NT, MODE, FK_FWD, 3, false, 1>(p, nblocks, s);
+        }
+        return hipErrorInvalidValue;
     }
     switch (kind) {
         case KIND_FWD: return launch_k<R, L, C, NT, MODE, FK_FWD, 3, false>(p, nblocks, s);

@@ -313,8 +313,13 @@ int lds_buffers_generic(int kind) {
 int choose_C(const vg_plan* p, const PassStep& st, bool* specialised) {
     *specialised = false;
     const PassDesc& d = st.desc;
+    // the specialised kernels cover the four-step steps of column passes:
+    // step A (forward + twiddle), step B (fused, full length) and A' (inverse)
     const bool four = d.post_tw != 0 || d.fs_L1 != 0;
-    if (!four && !std::getenv("VG_GENERIC_PASSES")) {
+    const bool four_ok = !four || (st.mode == MODE_COL && ((st.kind == KIND_FWD && d.post_tw == 1 && !d.fs_L1) ||
+                                                          ((st.kind == KIND_FUSED || st.kind == KIND_FUSED_GRAD) &&
+                                                           d.fs_L1 && d.post_tw == 2 && p->d == 2)));
+    if (four_ok && !std::getenv("VG_GENERIC_PASSES")) {
         const int fc = fast_pass_C(d.L, st.mode, p->fp64);
         const bool rowm = st.mode == MODE_ROW;
         if (fc > 0 && fast_pass_fits(d.L, st.mode, p->fp64, d.in_se, d.out_se, rowm ? d.in_so : 1, rowm ? d.out_so : 1)) {
@@ -401,16 +406,17 @@ void set_ws(Program& prog, const std::vector<size_t>& sizes_bytes) {
 }
 
 // Four-step split L = L1 * L2 of a long column axis: L1 even (the zero padding
-// of the first step is then its upper half), both factors as close to sqrt(L)
-// as possible.  0 if none exists.
-int four_step_L1(int L) {
+// of the first step is then its upper half), preferring factors with
+// specialised column kernels, then factors close to sqrt(L).  0 if none.
+int four_step_L1(int L, bool fp64) {
     int best = 0;
     double bestd = 1e30;
     for (int a = 2; a < L; a += 2) {
         if (L % a) continue;
         const int b = L / a;
         if (radix_plan(a).empty() || radix_plan(b).empty()) continue;
-        const double dd = std::fabs(std::log((double)a) - std::log((double)b));
+        const bool fast = fast_pass_C(a, MODE_COL, fp64) > 0 && fast_pass_C(b, MODE_COL, fp64) > 0;
+        const double dd = std::fabs(std::log((double)a) - std::log((double)b)) + (fast ? 0.0 : 100.0);
         if (dd < bestd - 1e-12) {
             bestd = dd;
             best = a;
@@ -489,7 +495,7 @@ vg_status build_programs(vg_plan* p, hipStream_t stream) {
                                        BUF_GRAD0 + 1));
             G.steps.push_back(row_step(p, KIND_INV, W1, RP, (int)L, BUF_GRAD0 + 0, N, (int)N, N, "g3_row_inv_d1"));
         } else {
-            const int L1 = four_step_L1((int)L);
+            const int L1 = four_step_L1((int)L, p->fp64);
             if (L1 == 0) return fail(VG_ERR_UNSUPPORTED_SIZE, "no four-step split of 2N");
             const int L2 = (int)(L / L1);
             const size_t bL = (size_t)(L * RP) * es;  // all L rows carry data between the steps

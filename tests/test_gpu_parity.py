@@ -180,7 +180,8 @@ def test_linearity_on_gpu():
 
 
 @pytest.mark.parametrize("d,N,kernel,k", [(3, 32, "helmholtz", 9.0), (3, 48, "laplace", 0.0),
-                                          (2, 128, "helmholtz", 30.0), (2, 512, "helmholtz", 60.0)])
+                                          (2, 128, "helmholtz", 30.0), (2, 512, "helmholtz", 60.0),
+                                          (2, 1024, "helmholtz", 50.0)])
 def test_specialised_and_generic_passes_agree(d, N, kernel, k, monkeypatch):
     """Lengths with a length-specialised kernel against the generic runtime-radix
     kernel (selected at plan creation by VG_GENERIC_PASSES)."""
