@@ -189,7 +189,11 @@ __device__ void run_fft(const PassDesc& p, const Tile& t, int src_kind, const cp
                             gdst[t.out_base0 + q * t.out_qstride + (long long)e * p.out_se] =
                                 p.post_tw ? post_twiddle(p, v[r], e, t.o) : v[r];
                     } else if (last && dst_kind == DST_TABLE) {
-                        out_l[lidx<MODE>(q, e, C, L)] = cmul(v[r], table_value<R>(p, e, t.col0 + q, t.o));
+                        // pencils past the end of a ragged tile take the last
+                        // valid column (their results are never stored): the
+                        // octant fold min(c, L - c) is negative for c > L
+                        const int col = t.col0 + min(q, t.nvalid - 1);
+                        out_l[lidx<MODE>(q, e, C, L)] = cmul(v[r], table_value<R>(p, e, col, t.o));
                     } else {
                         out_l[lidx<MODE>(q, e, C, L)] = v[r];
                     }
