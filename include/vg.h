@@ -149,15 +149,24 @@ vg_status vg_gradient(const vg_plan* plan, const void* f, void* phi, void* grad,
                       void* workspace, void* stream);
 
 /*
- * Apply `count` plans to `count` densities in one go: phi[i] = T_i * f[i].
- * Plans may mix d, N, kernel and k; all must share one precision.  The batch
- * runs as one persistent kernel launch whose workers take (density, pass,
- * tile) items in dependency order; the launch is captured in a HIP graph on
- * first use and replayed while (plans, pointers, workspace, stream) repeat.
+ * Apply `count` plans to `count` densities in one go: phi[i] = T_i * f[i]
+ * (Section 4 applied to a set of independent densities).  Plans may mix d, N,
+ * kernel and k; all must share one precision and live on the current device.
+ * f[i], phi[i]: device arrays as in vg_apply (phi[i] == f[i] allowed).
+ * Execution: stage s runs pass s of every density; densities whose pass s
+ * has the same specialised kernel share one grouped launch whose workgroups
+ * take (density, tile) items.  The launch sequence is captured in a HIP graph
+ * on the first call with a given (plans, f, phi, workspace) and replayed on
+ * later calls with the same arguments (the library keeps the last 8 such
+ * batches; destroying a plan drops the batches that use it).
+ * The call may itself be recorded into the caller's stream capture once the
+ * same arguments have been used in one call outside capture.
  * workspace: at least vg_batched_workspace_size bytes, or NULL (an internal
  * buffer owned by the library; such calls must not overlap in time).
- * Errors: VG_ERR_INVALID_ARG (count <= 0, NULL entries, mixed precision),
- * VG_ERR_DEVICE.
+ * Errors: VG_ERR_INVALID_ARG (count <= 0, NULL entries, mixed precision, a
+ * plan of another device), VG_ERR_NOT_CAPTURABLE (first use of these
+ * arguments, or growth of the internal workspace, under stream capture),
+ * VG_ERR_OUT_OF_MEMORY, VG_ERR_DEVICE.
  */
 size_t vg_batched_workspace_size(int count, const vg_plan* const* plans);
 vg_status vg_apply_batched(int count, const vg_plan* const* plans,

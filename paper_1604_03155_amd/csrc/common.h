@@ -110,9 +110,26 @@ struct GreensParams {
     double window;
 };
 
+// Grouped launch of one specialised pass over several arrays: device arrays
+// of nitems descriptors and nitems + 1 workgroup offsets (starts[nitems] =
+// ntiles, the grid size).
+struct GroupArgs {
+    const PassDesc* descs;
+    const unsigned* starts;
+    int nitems;
+    unsigned ntiles;
+};
+
 // ------------------------------------------------------------- launchers --
 // All return hipSuccess or the first HIP error.
 hipError_t launch_fft_pass(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
+// Grouped specialised pass; `proto` is any of the group's descriptors (the
+// launch shape comes from it).  hipErrorInvalidValue if the length has no
+// grouped kernel.
+hipError_t launch_fast_group(const PassDesc& proto, const GroupArgs& g, int mode, int kind, bool fp64,
+                             hipStream_t s);
+// Whether launch_fast_group covers passes of length L.
+bool fast_group_supported(int L);
 size_t fft_pass_lds_bytes(const PassDesc& p, int kind, bool fp64);
 
 hipError_t launch_greens_contract(const GreensParams& g, int M2, int n_out, const double* cmat,

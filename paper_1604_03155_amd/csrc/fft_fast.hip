@@ -94,4 +94,31 @@ hipError_t launch_fast_pass(const PassDesc& p, int mode, int kind, bool fp64, hi
     }
 }
 
+// grouped kernels
+hipError_t launch_fast_group_32(const PassDesc& proto, const GroupArgs& g, int mode, int kind, bool fp64, hipStream_t s);
+hipError_t launch_fast_group_64(const PassDesc& proto, const GroupArgs& g, int mode, int kind, bool fp64, hipStream_t s);
+hipError_t launch_fast_group_96(const PassDesc& proto, const GroupArgs& g, int mode, int kind, bool fp64, hipStream_t s);
+hipError_t launch_fast_group_128(const PassDesc& proto, const GroupArgs& g, int mode, int kind, bool fp64, hipStream_t s);
+hipError_t launch_fast_group_192(const PassDesc& proto, const GroupArgs& g, int mode, int kind, bool fp64, hipStream_t s);
+hipError_t launch_fast_group_256(const PassDesc& proto, const GroupArgs& g, int mode, int kind, bool fp64, hipStream_t s);
+hipError_t launch_fast_group_512(const PassDesc& proto, const GroupArgs& g, int mode, int kind, bool fp64, hipStream_t s);
+hipError_t launch_fast_group_1024(const PassDesc& proto, const GroupArgs& g, int mode, int kind, bool fp64, hipStream_t s);
+
+bool fast_group_supported(int L) { return L == 32 || L == 64 || L == 96 || L == 128 || L == 192 || L == 256 || L == 512 || L == 1024; }
+
+hipError_t launch_fast_group(const PassDesc& proto, const GroupArgs& g, int mode, int kind, bool fp64, hipStream_t s) {
+    if (g.nitems <= 0 || g.ntiles == 0) return hipSuccess;
+    switch (proto.L) {
+        case 32: return launch_fast_group_32(proto, g, mode, kind, fp64, s);
+        case 64: return launch_fast_group_64(proto, g, mode, kind, fp64, s);
+        case 96: return launch_fast_group_96(proto, g, mode, kind, fp64, s);
+        case 128: return launch_fast_group_128(proto, g, mode, kind, fp64, s);
+        case 192: return launch_fast_group_192(proto, g, mode, kind, fp64, s);
+        case 256: return launch_fast_group_256(proto, g, mode, kind, fp64, s);
+        case 512: return launch_fast_group_512(proto, g, mode, kind, fp64, s);
+        case 1024: return launch_fast_group_1024(proto, g, mode, kind, fp64, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace vg

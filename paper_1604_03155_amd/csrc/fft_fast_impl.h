@@ -497,9 +497,9 @@ __device__ __forceinline__ void tile_body(cplx<R>* v, cplx<R>* kt, cplx<R>* lds,
     }
 }
 
-// One tile per workgroup.
+// One tile (tile index b of the pass described by p).
 template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX, int FS>
-__global__ void __launch_bounds__(NT) fast_kernel(PassDesc p) {
+__device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
     constexpr RP F = make_plan(L, kMaxRad<R>);
     constexpr RP I = reversed(F);
     constexpr int E = C * L / NT;
@@ -509,7 +509,7 @@ __global__ void __launch_bounds__(NT) fast_kernel(PassDesc p) {
     using LY = Lay<L, C, MODE, (int)sizeof(cplx<R>)>;
     __shared__ cplx<R> lds[LY::size];
     const int t = threadIdx.x;
-    const FTile tl = fast_tile<C, MODE>(p, xcd_tile(blockIdx.x, gridDim.x));
+    const FTile tl = fast_tile<C, MODE>(p, b);
     const cplx<R>* __restrict__ gin = reinterpret_cast<const cplx<R>*>(p.in);
     cplx<R> vn[LoadSet<R, L, C, NT, PL, NIN>::NV];
     cplx<R> v[E];
@@ -523,16 +523,40 @@ __global__ void __launch_bounds__(NT) fast_kernel(PassDesc p) {
     tile_body<R, L, C, NT, MODE, FK, D, CPLX, FS>(v, kt, lds, tl, p, t);
 }
 
+// One tile per workgroup.
+template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX, int FS>
+__global__ void __launch_bounds__(NT) fast_kernel(PassDesc p) {
+    fast_run<R, L, C, NT, MODE, FK, D, CPLX, FS>(p, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// Grouped launch: the same pass over several independent arrays (one
+// descriptor each, same length and kind); item i owns the workgroups
+// [starts[i], starts[i + 1]).
+template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX, int FS>
+__global__ void __launch_bounds__(NT) fast_group_kernel(const PassDesc* __restrict__ descs,
+                                                       const unsigned* __restrict__ starts, int nitems) {
+    const unsigned b = xcd_tile(blockIdx.x, gridDim.x);
+    int i = 0;
+    while (i + 1 < nitems && b >= starts[i + 1]) ++i;
+    fast_run<R, L, C, NT, MODE, FK, D, CPLX, FS>(descs[i], b - starts[i]);
+}
+
 // --------------------------------------------------------------- dispatch --
-template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX, int FS = 0>
-hipError_t launch_k(const PassDesc& p, long long ntiles, hipStream_t s) {
-    hipLaunchKernelGGL((fast_kernel<R, L, C, NT, MODE, FK, D, CPLX, FS>), dim3((unsigned)ntiles), dim3(NT), 0, s, p);
+template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX, int FS = 0, bool GROUP = false>
+hipError_t launch_k(const PassDesc& p, long long ntiles, hipStream_t s, const GroupArgs* g) {
+    if constexpr (GROUP) {
+        hipLaunchKernelGGL((fast_group_kernel<R, L, C, NT, MODE, FK, D, CPLX, FS>), dim3(g->ntiles), dim3(NT), 0, s,
+                           g->descs, g->starts, g->nitems);
+    } else {
+        hipLaunchKernelGGL((fast_kernel<R, L, C, NT, MODE, FK, D, CPLX, FS>), dim3((unsigned)ntiles), dim3(NT), 0, s, p);
+    }
     return hipGetLastError();
 }
 
-template <typename R, int L, int C, int NT, int MODE>
-hipError_t launch_shape(const PassDesc& p, int kind, hipStream_t s) {
-    long long nblocks = MODE == MODE_COL ? (long long)p.outer * ((p.inner + C - 1) / C) : (p.outer + C - 1) / C;
+template <typename R, int L, int C, int NT, int MODE, bool GROUP>
+hipError_t launch_shape(const PassDesc& p, int kind, hipStream_t s, const GroupArgs* ga) {
+    long long nblocks = GROUP ? (long long)ga->ntiles
+                              : (MODE == MODE_COL ? (long long)p.outer * ((p.inner + C - 1) / C) : (p.outer + C - 1) / C);
     if (nblocks <= 0) return hipSuccess;
     if (nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     const bool fused = kind == KIND_FUSED || kind == KIND_FUSED_GRAD;
@@ -543,37 +567,37 @@ hipError_t launch_shape(const PassDesc& p, int kind, hipStream_t s) {
         const bool g = kind == KIND_FUSED_GRAD;
         if (p.d != 2 || p.post_tw != 2) return hipErrorInvalidValue;
         if (p.table_complex)
-            return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 2, true, 2>(p, nblocks, s)
-                     : launch_k<R, L, C, NT, MODE, FK_FUSED, 2, true, 2>(p, nblocks, s);
-        return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 2, false, 2>(p, nblocks, s)
-                 : launch_k<R, L, C, NT, MODE, FK_FUSED, 2, false, 2>(p, nblocks, s);
+            return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 2, true, 2, GROUP>(p, nblocks, s, ga)
+                     : launch_k<R, L, C, NT, MODE, FK_FUSED, 2, true, 2, GROUP>(p, nblocks, s, ga);
+        return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 2, false, 2, GROUP>(p, nblocks, s, ga)
+                 : launch_k<R, L, C, NT, MODE, FK_FUSED, 2, false, 2, GROUP>(p, nblocks, s, ga);
     } else if (fused) {
         const bool g = kind == KIND_FUSED_GRAD;
         if (p.d == 3 && p.table_complex)
-            return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 3, true>(p, nblocks, s)
-                     : launch_k<R, L, C, NT, MODE, FK_FUSED, 3, true>(p, nblocks, s);
+            return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 3, true, 0, GROUP>(p, nblocks, s, ga)
+                     : launch_k<R, L, C, NT, MODE, FK_FUSED, 3, true, 0, GROUP>(p, nblocks, s, ga);
         if (p.d == 3)
-            return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 3, false>(p, nblocks, s)
-                     : launch_k<R, L, C, NT, MODE, FK_FUSED, 3, false>(p, nblocks, s);
+            return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 3, false, 0, GROUP>(p, nblocks, s, ga)
+                     : launch_k<R, L, C, NT, MODE, FK_FUSED, 3, false, 0, GROUP>(p, nblocks, s, ga);
         if (p.table_complex)
-            return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 2, true>(p, nblocks, s)
-                     : launch_k<R, L, C, NT, MODE, FK_FUSED, 2, true>(p, nblocks, s);
-        return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 2, false>(p, nblocks, s)
-                 : launch_k<R, L, C, NT, MODE, FK_FUSED, 2, false>(p, nblocks, s);
+            return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 2, true, 0, GROUP>(p, nblocks, s, ga)
+                     : launch_k<R, L, C, NT, MODE, FK_FUSED, 2, true, 0, GROUP>(p, nblocks, s, ga);
+        return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 2, false, 0, GROUP>(p, nblocks, s, ga)
+                 : launch_k<R, L, C, NT, MODE, FK_FUSED, 2, false, 0, GROUP>(p, nblocks, s, ga);
     }
     if (p.post_tw || p.fs_L1) {
         // four-step step A (column forward with post twiddle)
         if constexpr (MODE == MODE_COL) {
             if (kind == KIND_FWD && p.post_tw == 1 && !p.fs_L1)
-                return launch_k<R, L, C, NT, MODE, FK_FWD, 3, false, 1>(p, nblocks, s);
+                return launch_k<R, L, C, NT, MODE, FK_FWD, 3, false, 1, GROUP>(p, nblocks, s, ga);
         }
         return hipErrorInvalidValue;
     }
     switch (kind) {
-        case KIND_FWD: return launch_k<R, L, C, NT, MODE, FK_FWD, 3, false>(p, nblocks, s);
-        case KIND_INV: return launch_k<R, L, C, NT, MODE, FK_INV, 3, false>(p, nblocks, s);
-        case KIND_INV_GRAD: return launch_k<R, L, C, NT, MODE, FK_INV_GRAD, 3, false>(p, nblocks, s);
-        case 100 + KIND_INV: return launch_k<R, L, C, NT, MODE, FK_INV_DERIV, 3, false>(p, nblocks, s);
+        case KIND_FWD: return launch_k<R, L, C, NT, MODE, FK_FWD, 3, false, 0, GROUP>(p, nblocks, s, ga);
+        case KIND_INV: return launch_k<R, L, C, NT, MODE, FK_INV, 3, false, 0, GROUP>(p, nblocks, s, ga);
+        case KIND_INV_GRAD: return launch_k<R, L, C, NT, MODE, FK_INV_GRAD, 3, false, 0, GROUP>(p, nblocks, s, ga);
+        case 100 + KIND_INV: return launch_k<R, L, C, NT, MODE, FK_INV_DERIV, 3, false, 0, GROUP>(p, nblocks, s, ga);
         default: return hipErrorInvalidValue;
     }
 }
@@ -604,23 +628,23 @@ constexpr Shape shape_for(int L, int mode, int esize) {
 
 // ROWS_ONLY: long lengths are instantiated for row passes only (their column
 // passes use the four-step decomposition).
-template <typename R, int L, int MODE>
-hipError_t launch_len_mode(const PassDesc& p, int kind, hipStream_t s) {
+template <typename R, int L, int MODE, bool GROUP>
+hipError_t launch_len_mode(const PassDesc& p, int kind, hipStream_t s, const GroupArgs* ga) {
     constexpr Shape S = shape_for(L, MODE, (int)sizeof(cplx<R>));
     if constexpr (S.C == 0) {
         return hipErrorInvalidValue;
     } else {
         static_assert(S.C * L % S.E == 0 && S.NT >= 64 && S.NT <= 1024, "bad launch shape");
         if (p.C != S.C) return hipErrorInvalidValue;
-        return launch_shape<R, L, S.C, S.NT, MODE>(p, kind, s);
+        return launch_shape<R, L, S.C, S.NT, MODE, GROUP>(p, kind, s, ga);
     }
 }
 
-template <typename R, int L, bool ROWS_ONLY>
-hipError_t launch_len(const PassDesc& p, int mode, int kind, hipStream_t s) {
-    if (mode == MODE_ROW) return launch_len_mode<R, L, MODE_ROW>(p, kind, s);
+template <typename R, int L, bool ROWS_ONLY, bool GROUP = false>
+hipError_t launch_len(const PassDesc& p, int mode, int kind, hipStream_t s, const GroupArgs* ga = nullptr) {
+    if (mode == MODE_ROW) return launch_len_mode<R, L, MODE_ROW, GROUP>(p, kind, s, ga);
     if constexpr (ROWS_ONLY) return hipErrorInvalidValue;
-    else return launch_len_mode<R, L, MODE_COL>(p, kind, s);
+    else return launch_len_mode<R, L, MODE_COL, GROUP>(p, kind, s, ga);
 }
 
 // Whether the 32-bit lane offsets of the specialised kernel cover a pass
@@ -673,6 +697,15 @@ int shape_C(int mode) {
     hipError_t launch_fast_##LL(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s) {           \
         return fp64 ? fastfft::launch_len<double, LL, ROWS_ONLY>(p, mode, kind, s)                           \
                     : fastfft::launch_len<float, LL, ROWS_ONLY>(p, mode, kind, s);                           \
+    }
+
+// Grouped launches (one translation unit per length, separate from the
+// single-array kernels so that both compile in parallel).
+#define VG_FAST_GROUP_INSTANTIATE(LL)                                                                        \
+    hipError_t launch_fast_group_##LL(const PassDesc& proto, const GroupArgs& g, int mode, int kind, bool fp64, \
+                                      hipStream_t s) {                                                       \
+        return fp64 ? fastfft::launch_len<double, LL, false, true>(proto, mode, kind, s, &g)                 \
+                    : fastfft::launch_len<float, LL, false, true>(proto, mode, kind, s, &g);                 \
     }
 
 }  // namespace vg

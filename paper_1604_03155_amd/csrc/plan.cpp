@@ -573,8 +573,8 @@ void finalize_bytes(vg_plan* p) {
         for (PassStep& s : pr->steps) s.bytes = pass_bytes(p, s);
 }
 
-vg_status run_program(const vg_plan* p, const Program& prog, const void* f, void* phi, void* grad, void* ws,
-                      hipStream_t stream) {
+std::vector<BoundStep> bind_program(const vg_plan* p, const Program& prog, const void* f, void* phi, void* grad,
+                                    void* ws) {
     const long long N = p->N;
     long long V = 1;
     for (int i = 0; i < p->d; ++i) V *= N;
@@ -587,21 +587,36 @@ vg_status run_program(const vg_plan* p, const Program& prog, const void* f, void
         if (id >= BUF_WS0 && id < BUF_WS0 + 8) return static_cast<unsigned char*>(ws) + prog.ws_offsets[id - BUF_WS0];
         return nullptr;
     };
-    void* mark = profiler_mark(stream);
+    std::vector<BoundStep> out;
+    out.reserve(prog.steps.size());
     for (const PassStep& st : prog.steps) {
-        PassDesc d = st.desc;
-        d.table = p->table;  // programs are built before the precompute fills the table
-        d.in = resolve(st.in_buf);
-        d.out = resolve(st.out_buf);
-        d.out2 = resolve(st.out2_buf);
-        int kind = st.kind;
-        if (kind == KIND_INV_GRAD && d.out == nullptr) {
+        BoundStep b;
+        b.desc = st.desc;
+        b.desc.table = p->table;  // programs are built before the precompute fills the table
+        b.desc.in = resolve(st.in_buf);
+        b.desc.out = resolve(st.out_buf);
+        b.desc.out2 = resolve(st.out2_buf);
+        b.kind = st.kind;
+        if (b.kind == KIND_INV_GRAD && b.desc.out == nullptr) {
             // gradient without phi: derivative-only inverse into out2
-            d.out = d.out2;
-            d.out2 = nullptr;
-            kind = 100 + KIND_INV;
+            b.desc.out = b.desc.out2;
+            b.desc.out2 = nullptr;
+            b.kind = 100 + KIND_INV;
         }
-        hipError_t e = launch_fft_pass(d, st.mode, kind, p->fp64, stream);
+        b.mode = st.mode;
+        b.name = st.name;
+        b.bytes = st.bytes;
+        out.push_back(b);
+    }
+    return out;
+}
+
+vg_status run_program(const vg_plan* p, const Program& prog, const void* f, void* phi, void* grad, void* ws,
+                      hipStream_t stream) {
+    const std::vector<BoundStep> steps = bind_program(p, prog, f, phi, grad, ws);
+    void* mark = profiler_mark(stream);
+    for (const BoundStep& st : steps) {
+        hipError_t e = launch_fft_pass(st.desc, st.mode, st.kind, p->fp64, stream);
         if (e != hipSuccess) return from_hip(e, st.name);
         if (mark) {
             void* next = profiler_mark(stream);

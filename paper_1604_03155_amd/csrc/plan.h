@@ -72,6 +72,16 @@ std::vector<int> radix_plan(int L);
 // tables they need); VG_ERR_UNSUPPORTED_SIZE if some pass cannot run.
 vg_status build_programs(vg_plan* p, hipStream_t s);
 
+// A program step with its buffers bound to device addresses.
+struct BoundStep {
+    PassDesc desc;
+    int mode, kind;
+    const char* name;
+    double bytes;
+};
+std::vector<BoundStep> bind_program(const vg_plan* p, const Program& prog, const void* f, void* phi, void* grad,
+                                    void* ws);
+
 // Run a program: bind buffers and launch every step on `stream`.
 vg_status run_program(const vg_plan* p, const Program& prog, const void* f, void* phi, void* grad,
                       void* ws, hipStream_t stream);

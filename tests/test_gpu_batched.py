@@ -1,0 +1,227 @@
+"""GPU: batched applies over plans of mixed d, N, kernel and k.
+
+The batch runs stage by stage with grouped launches (one launch per stage and
+kernel shape, workgroups taking (density, tile) items) captured in a HIP graph.
+Every tile runs the same code as in a single-plan apply, so batched results
+must equal single applies bit for bit; a sample of the mixed 64-density batch
+is also checked against the FP64 oracle at the FP32 bar (relative L2 1e-5).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _vg():
+    import paper_1604_03155_amd as vg
+    return vg
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def random_density(seed, d, N):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal((N,) * d) + 1j * rng.standard_normal((N,) * d)).astype(np.complex128)
+
+
+def dev(f, precision="fp32"):
+    torch = _torch()
+    dt = torch.complex128 if precision == "fp64" else torch.complex64
+    return torch.from_numpy(f).to(dtype=dt, device="cuda").contiguous()
+
+
+@pytest.fixture(scope="module")
+def c4():
+    """The 64-density mixed batch (N in {48, 64, 96, 128}, Laplace and
+    Helmholtz k ~ U[5, 40]) with FP32 plans and its densities on the device."""
+    from workloads import batch_workload, evaluate_grid
+    vg = _vg()
+    items = batch_workload()
+    plans, fs_host, fs = [], [], []
+    for prm, src in items:
+        plans.append(vg.Plan(3, prm["N"], prm["kernel"], prm["k"], precision="fp32"))
+        f = evaluate_grid(src, prm["N"])
+        fs_host.append(f)
+        fs.append(dev(f))
+    return items, plans, fs_host, fs
+
+
+def singles(plans, fs):
+    return [p.apply(f) for p, f in zip(plans, fs)]
+
+
+def test_c4_batch_bitwise_equals_single_applies(c4):
+    say("c4 bitwise")
+    vg = _vg()
+    torch = _torch()
+    _, plans, _, fs = c4
+    ref = singles(plans, fs)
+    out = vg.apply_batched(plans, fs)
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(out, ref)):
+        assert torch.equal(a, b), i
+
+
+def test_c4_batch_sample_against_oracle(c4):
+    """Two densities of every size (one Laplace, one Helmholtz where the draw
+    has both) against the FP64 oracle."""
+    say("c4 oracle sample")
+    from oracle import operator as op
+    vg = _vg()
+    torch = _torch()
+    items, plans, fs_host, fs = c4
+    out = vg.apply_batched(plans, fs)
+    torch.cuda.synchronize()
+    picked = {}
+    for i, (prm, _) in enumerate(items):
+        key = (prm["N"], prm["kernel"])
+        picked.setdefault(key, i)
+    assert len(picked) == 8
+    for (N, kernel), i in sorted(picked.items()):
+        prm = items[i][0]
+        say("  oracle", i, N, kernel, prm["k"])
+        o = op.Plan(3, N, kernel, prm["k"])
+        assert rel_l2(out[i].cpu().numpy(), o.apply(fs_host[i])) <= FP32_TOL, i
+
+
+def test_c4_graph_replays_track_new_density_values(c4):
+    """Same arrays, new contents: the captured graph replays (with eager work
+    and synchronisations in between) and every replay matches single applies."""
+    say("c4 replays")
+    vg = _vg()
+    torch = _torch()
+    _, plans, _, fs = c4
+    work = [f.clone() for f in fs]
+    outs = [torch.empty_like(f) for f in fs]
+    for r in range(3):
+        for j, w in enumerate(work):
+            w.mul_(complex(0.5 + 0.25 * r, 0.1 * (j % 3)))
+        scratch = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        vg.apply_batched(plans, work, outs)
+        torch.cuda.synchronize()
+        assert torch.isfinite(scratch)
+        ref = singles(plans, work)
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(outs, ref)):
+            assert torch.equal(a, b), (r, i)
+
+
+def test_c4_explicit_workspace_and_stream(c4):
+    say("c4 workspace/stream")
+    vg = _vg()
+    torch = _torch()
+    _, plans, _, fs = c4
+    nbytes = vg.batched_workspace_size(plans)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    outs = [torch.empty_like(f) for f in fs]
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        vg.apply_batched(plans, fs, outs, workspace=ws, stream=s)
+    s.synchronize()
+    ref = singles(plans, fs)
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(outs, ref)):
+        assert torch.equal(a, b), i
+
+
+def test_batched_mixed_dimensions_and_ungrouped_paths(monkeypatch):
+    """2D and 3D plans in one batch, duplicated sizes (grouped launches) and
+    singletons; the same batch with grouping and graphs switched off agrees."""
+    say("mixed d")
+    vg = _vg()
+    torch = _torch()
+    specs = [(2, 64, "laplace", 0.0), (3, 32, "helmholtz", 9.0), (2, 64, "helmholtz", 10.0),
+             (3, 32, "laplace", 0.0), (2, 48, "helmholtz", 3.0), (3, 24, "helmholtz", 4.0),
+             (3, 32, "helmholtz", 12.0), (2, 64, "laplace", 0.0), (2, 512, "helmholtz", 40.0),
+             (2, 512, "laplace", 0.0)]
+    plans = [vg.Plan(d, N, kind, k, precision="fp32") for d, N, kind, k in specs]
+    fs = [dev(random_density(50 + i, d, N)) for i, (d, N, _, _) in enumerate(specs)]
+    ref = singles(plans, fs)
+    out = vg.apply_batched(plans, fs)
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(out, ref)):
+        assert torch.equal(a, b), i
+    monkeypatch.setenv("VG_BATCH_NO_GROUP", "1")
+    monkeypatch.setenv("VG_BATCH_NO_GRAPH", "1")
+    out2 = vg.apply_batched(plans, fs)  # new output arrays: a new batch entry
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(out2, ref)):
+        assert torch.equal(a, b), i
+
+
+def test_batched_fp64_matches_single_applies():
+    say("fp64 batch")
+    vg = _vg()
+    torch = _torch()
+    specs = [(3, 16, "helmholtz", 6.0), (3, 16, "laplace", 0.0), (3, 24, "helmholtz", 2.0), (2, 32, "laplace", 0.0)]
+    plans = [vg.Plan(d, N, kind, k, precision="fp64") for d, N, kind, k in specs]
+    fs = [dev(random_density(70 + i, d, N), "fp64") for i, (d, N, _, _) in enumerate(specs)]
+    ref = singles(plans, fs)
+    out = vg.apply_batched(plans, fs)
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(out, ref)):
+        assert torch.equal(a, b), i
+
+
+def test_batched_inside_caller_graph_capture():
+    """After one eager call with the same arrays, a batched apply can be
+    recorded into the caller's own graph; replays follow new density values."""
+    say("caller capture")
+    vg = _vg()
+    torch = _torch()
+    specs = [(3, 32, "helmholtz", 9.0), (3, 32, "helmholtz", 5.0), (3, 48, "laplace", 0.0)]
+    plans = [vg.Plan(d, N, kind, k, precision="fp32") for d, N, kind, k in specs]
+    fs = [dev(random_density(90 + i, d, N)) for i, (d, N, _, _) in enumerate(specs)]
+    outs = [torch.empty_like(f) for f in fs]
+    ws = torch.empty(vg.batched_workspace_size(plans), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        vg.apply_batched(plans, fs, outs, workspace=ws, stream=s)  # eager: builds the batch entry
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        vg.apply_batched(plans, fs, outs, workspace=ws, stream=s)
+    torch.cuda.synchronize()
+    for r in range(3):
+        for f in fs:
+            f.mul_(complex(0.0, 1.0 + r))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        ref = singles(plans, fs)
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(outs, ref)):
+            assert torch.equal(a, b), (r, i)
+
+
+def test_batched_first_call_under_capture_is_refused():
+    say("capture refusal")
+    vg = _vg()
+    torch = _torch()
+    plans = [vg.Plan(3, 16, "laplace", precision="fp32")]
+    fs = [dev(random_density(99, 3, 16))]
+    outs = [torch.empty_like(fs[0])]
+    ws = torch.empty(vg.batched_workspace_size(plans), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with pytest.raises(vg.VGError, match="NOT_CAPTURABLE|capture"):
+        with torch.cuda.graph(g, stream=s):
+            vg.apply_batched(plans, fs, outs, workspace=ws, stream=s)
+    torch.cuda.synchronize()
