@@ -69,10 +69,16 @@ typedef enum vg_precision {
     VG_FP64 = 1   /* complex128 end to end */
 } vg_precision;
 
+/* Plan-time autotuning: the apply program is timed (on zero arrays, on the
+ * plan's stream, synchronously) under candidate layouts and the fastest is
+ * kept for apply and gradient.  Candidates: pitch padding of the 2N x 2N
+ * planes (3D) / 2N rows (2D) of the intermediates, XCD-aware tile order of
+ * the specialised kernels, the four-step split 2N = L1 L2 of long 2D columns,
+ * and (full) every pass on the generic runtime-radix kernel. */
 typedef enum vg_tune_mode {
-    VG_TUNE_OFF = 0,    /* built-in launch shapes */
-    VG_TUNE_QUICK = 1,  /* time a few candidate shapes per pass at plan time */
-    VG_TUNE_FULL = 2    /* time every candidate shape */
+    VG_TUNE_OFF = 0,    /* built-in layout: 256-byte padding, XCD order, default split */
+    VG_TUNE_QUICK = 1,  /* padding {256, 0} x order {XCD, launch} (x 3 splits in 2D), 3 timed applies each */
+    VG_TUNE_FULL = 2    /* padding {0, 256, 512, 1024} x order x 6 splits, plus generic kernels, 10 applies each */
 } vg_tune_mode;
 
 typedef struct vg_plan vg_plan;
@@ -98,6 +104,13 @@ typedef struct vg_plan_info {
     size_t table_bytes;       /* bytes of the Khat octant kept for applies */
     size_t workspace_bytes;   /* vg_workspace_size */
     size_t gradient_workspace_bytes;
+    int tune;                 /* vg_tune_mode the plan was created with */
+    double tune_ms;           /* host wall time of the autotuner (0 without tuning) */
+    int tune_candidates;      /* layouts timed */
+    int pad_bytes;            /* chosen layout: pitch padding of the intermediates */
+    int xcd_map;              /* 1: XCD-aware tile order */
+    int four_step_L1;         /* four-step split of long 2D columns (0: default / none) */
+    int generic_passes;       /* 1: all passes on the generic kernel */
 } vg_plan_info;
 
 /*

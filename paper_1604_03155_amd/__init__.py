@@ -43,7 +43,10 @@ class _Info(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int), ("N", ctypes.c_int), ("kernel", ctypes.c_int), ("precision", ctypes.c_int),
                 ("k", ctypes.c_double), ("L", ctypes.c_double), ("P", ctypes.c_int),
                 ("precompute_ms", ctypes.c_double), ("table_bytes", ctypes.c_size_t),
-                ("workspace_bytes", ctypes.c_size_t), ("gradient_workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("gradient_workspace_bytes", ctypes.c_size_t),
+                ("tune", ctypes.c_int), ("tune_ms", ctypes.c_double), ("tune_candidates", ctypes.c_int),
+                ("pad_bytes", ctypes.c_int), ("xcd_map", ctypes.c_int), ("four_step_L1", ctypes.c_int),
+                ("generic_passes", ctypes.c_int)]
 
 
 class _PassTime(ctypes.Structure):

@@ -124,6 +124,8 @@ vg_status vg_plan_create_ex(int d, int N, vg_kernel kernel, double k, const vg_p
         if (st != VG_OK) return st;
         st = precompute(p.get(), s, o.keep_operator != 0);
         if (st != VG_OK) return st;
+        st = autotune(p.get(), s);
+        if (st != VG_OK) return st;
         *out = p.release();
         return VG_OK;
     });
@@ -144,6 +146,13 @@ vg_status vg_plan_get_info(const vg_plan* p, vg_plan_info* info) {
     info->table_bytes = p->table_bytes;
     info->workspace_bytes = p->apply_prog.ws_bytes;
     info->gradient_workspace_bytes = p->grad_prog.ws_bytes;
+    info->tune = p->tune;
+    info->tune_ms = p->tune_ms;
+    info->tune_candidates = p->tune_candidates;
+    info->pad_bytes = p->cfg.pad_bytes;
+    info->xcd_map = p->cfg.xcd_map;
+    info->four_step_L1 = p->cfg.fs_L1;
+    info->generic_passes = p->cfg.generic;
     return VG_OK;
 }
 

@@ -94,6 +94,9 @@ struct PassDesc {
     int L_big;
     int post_tw;
     int fs_L1;
+    // specialised kernels: 1 maps workgroup slots to tiles XCD by XCD (each
+    // of the 8 XCDs gets a contiguous range of tiles), 0 keeps launch order
+    int xcd_map;
 };
 
 // ----------------------------------------------------- plan precompute ----

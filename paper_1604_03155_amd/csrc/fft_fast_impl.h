@@ -526,7 +526,7 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
 // One tile per workgroup.
 template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX, int FS>
 __global__ void __launch_bounds__(NT) fast_kernel(PassDesc p) {
-    fast_run<R, L, C, NT, MODE, FK, D, CPLX, FS>(p, xcd_tile(blockIdx.x, gridDim.x));
+    fast_run<R, L, C, NT, MODE, FK, D, CPLX, FS>(p, p.xcd_map ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x);
 }
 
 // Grouped launch: the same pass over several independent arrays (one

@@ -2,6 +2,7 @@
 // (Sections 2 and 4), twiddles, and the pass programs of apply and gradient.
 #include "plan.h"
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdlib>
@@ -319,7 +320,7 @@ int choose_C(const vg_plan* p, const PassStep& st, bool* specialised) {
     const bool four_ok = !four || (st.mode == MODE_COL && ((st.kind == KIND_FWD && d.post_tw == 1 && !d.fs_L1) ||
                                                           ((st.kind == KIND_FUSED || st.kind == KIND_FUSED_GRAD) &&
                                                            d.fs_L1 && d.post_tw == 2 && p->d == 2)));
-    if (four_ok && !std::getenv("VG_GENERIC_PASSES")) {
+    if (four_ok && !p->cfg.generic && !std::getenv("VG_GENERIC_PASSES")) {
         const int fc = fast_pass_C(d.L, st.mode, p->fp64);
         const bool rowm = st.mode == MODE_ROW;
         if (fc > 0 && fast_pass_fits(d.L, st.mode, p->fp64, d.in_se, d.out_se, rowm ? d.in_so : 1, rowm ? d.out_so : 1)) {
@@ -405,33 +406,30 @@ void set_ws(Program& prog, const std::vector<size_t>& sizes_bytes) {
     prog.ws_bytes = off;
 }
 
-// Four-step split L = L1 * L2 of a long column axis: L1 even (the zero padding
-// of the first step is then its upper half), preferring factors with
-// specialised column kernels, then factors close to sqrt(L).  0 if none.
-int four_step_L1(int L, bool fp64) {
-    int best = 0;
-    double bestd = 1e30;
+}  // namespace
+
+std::vector<int> four_step_splits(int L, bool fp64) {
+    std::vector<std::pair<double, int>> c;
     for (int a = 2; a < L; a += 2) {
         if (L % a) continue;
         const int b = L / a;
         if (radix_plan(a).empty() || radix_plan(b).empty()) continue;
         const bool fast = fast_pass_C(a, MODE_COL, fp64) > 0 && fast_pass_C(b, MODE_COL, fp64) > 0;
-        const double dd = std::fabs(std::log((double)a) - std::log((double)b)) + (fast ? 0.0 : 100.0);
-        if (dd < bestd - 1e-12) {
-            bestd = dd;
-            best = a;
-        }
+        c.push_back({std::fabs(std::log((double)a) - std::log((double)b)) + (fast ? 0.0 : 100.0), a});
     }
-    return best;
+    std::stable_sort(c.begin(), c.end(), [](const auto& x, const auto& y) { return x.first < y.first - 1e-12; });
+    std::vector<int> out;
+    for (auto& e : c) out.push_back(e.second);
+    return out;
 }
 
-}  // namespace
 
 void finalize_bytes(vg_plan* p);
 
 // Intermediate layouts.  A column tile whose rows are a large power of two
 // apart (a whole 2N x 2N plane in 3D, a 2N row in 2D) keeps hitting the same
-// HBM channels, so those pitches are lengthened by 256 bytes.
+// HBM channels, so those pitches are lengthened by cfg.pad_bytes (256 unless
+// the autotuner picks another value).
 //
 // A 2D column axis too long for one LDS-resident pencil runs as four steps
 // (L = L1 L2, n = L2 n1 + n2, k = k1 + L1 k2):
@@ -444,7 +442,7 @@ void finalize_bytes(vg_plan* p);
 vg_status build_programs(vg_plan* p, hipStream_t stream) {
     const long long N = p->N, L = 2 * N;
     const size_t es = p->fp64 ? 16 : 8;
-    const long long PAD = 256 / (long long)es;
+    const long long PAD = (long long)p->cfg.pad_bytes / (long long)es;
     const int W0 = BUF_WS0, W1 = BUF_WS0 + 1, W2 = BUF_WS0 + 2, W3 = BUF_WS0 + 3, W4 = BUF_WS0 + 4;
     Program& A = p->apply_prog;
     Program& G = p->grad_prog;
@@ -495,8 +493,10 @@ vg_status build_programs(vg_plan* p, hipStream_t stream) {
                                        BUF_GRAD0 + 1));
             G.steps.push_back(row_step(p, KIND_INV, W1, RP, (int)L, BUF_GRAD0 + 0, N, (int)N, N, "g3_row_inv_d1"));
         } else {
-            const int L1 = four_step_L1((int)L, p->fp64);
-            if (L1 == 0) return fail(VG_ERR_UNSUPPORTED_SIZE, "no four-step split of 2N");
+            const std::vector<int> splits = four_step_splits((int)L, p->fp64);
+            if (splits.empty()) return fail(VG_ERR_UNSUPPORTED_SIZE, "no four-step split of 2N");
+            int L1 = splits[0];
+            if (p->cfg.fs_L1 && std::find(splits.begin(), splits.end(), p->cfg.fs_L1) != splits.end()) L1 = p->cfg.fs_L1;
             const int L2 = (int)(L / L1);
             const size_t bL = (size_t)(L * RP) * es;  // all L rows carry data between the steps
             auto stepA = [&](int kind, int buf, const char* name) {
@@ -544,6 +544,7 @@ vg_status build_programs(vg_plan* p, hipStream_t stream) {
                 if (s2 != VG_OK) return s2;
                 st.desc.tw_big = p->twiddles[st.desc.L_big];
             }
+            st.desc.xcd_map = p->cfg.xcd_map;
             bool spec = false;
             st.desc.C = choose_C(p, st, &spec);
             st.desc.specialised = spec ? 1 : 0;

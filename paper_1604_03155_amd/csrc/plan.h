@@ -39,8 +39,25 @@ struct Program {
 
 }  // namespace vg
 
+namespace vg {
+// Layout and kernel choices of a plan's programs (the autotuner's search
+// space).  pad_bytes: extra pitch of the 2N x 2N planes (3D) / 2N rows (2D)
+// of the intermediates; xcd_map: XCD-aware tile order in the specialised
+// kernels; fs_L1: first factor of the four-step split of long 2D columns (0:
+// the default choice); generic: run every pass on the generic kernel.
+struct LayoutConfig {
+    int pad_bytes = 256;
+    int xcd_map = 1;
+    int fs_L1 = 0;
+    int generic = 0;
+};
+}  // namespace vg
+
 struct vg_plan {
     int d = 0, N = 0, kernel = 0, precision = 0, P = 4, tune = 0;
+    vg::LayoutConfig cfg;
+    double tune_ms = 0.0;     // wall time of the autotuner
+    int tune_candidates = 0;  // configurations timed
     double k = 0.0, L = 0.0;
     int device = 0;
     bool fp64 = false;
@@ -68,9 +85,19 @@ vg_status from_hip(hipError_t e, const char* what);
 // another prime factor.
 std::vector<int> radix_plan(int L);
 
-// Build the apply / gradient programs for a plan (allocates the twiddle
-// tables they need); VG_ERR_UNSUPPORTED_SIZE if some pass cannot run.
+// Build the apply / gradient programs for a plan with its layout config
+// p->cfg (allocates the twiddle tables they need); VG_ERR_UNSUPPORTED_SIZE if
+// some pass cannot run.
 vg_status build_programs(vg_plan* p, hipStream_t s);
+
+// Autotuner (tune.cpp): with p->tune != VG_TUNE_OFF, time the apply program
+// under candidate layout configs and keep the fastest (programs rebuilt).
+vg_status autotune(vg_plan* p, hipStream_t s);
+
+// Four-step splits L = L1 * L2 of a long 2D column axis usable by the plan
+// (L1 even, both factors with radix plans), nearest to sqrt(L) first, those
+// with specialised kernels for both factors before the others.
+std::vector<int> four_step_splits(int L, bool fp64);
 
 // A program step with its buffers bound to device addresses.
 struct BoundStep {

@@ -225,3 +225,30 @@ def test_batched_first_call_under_capture_is_refused():
         with torch.cuda.graph(g, stream=s):
             vg.apply_batched(plans, fs, outs, workspace=ws, stream=s)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("d,N,kernel,k,tune", [(3, 64, "helmholtz", 20.0, "quick"), (3, 48, "laplace", 0.0, "full"),
+                                               (2, 2048, "laplace", 0.0, "quick"), (2, 128, "helmholtz", 30.0, "full")])
+def test_autotuned_plans_agree_with_default_layout(d, N, kernel, k, tune):
+    """Plans built with the autotuner (timed layouts: pitch padding, tile
+    order, four-step split, generic kernels) compute the same operator: equal
+    to the default plan to FP32 rounding, bitwise when the default layout won."""
+    say("autotune", d, N, kernel, k, tune)
+    vg = _vg()
+    torch = _torch()
+    f = dev(random_density(120 + N, d, N))
+    base = vg.Plan(d, N, kernel, k, precision="fp32")
+    tuned = vg.Plan(d, N, kernel, k, precision="fp32", tune=tune)
+    info = tuned.info
+    say("  chosen", {key: info[key] for key in ("tune_ms", "tune_candidates", "pad_bytes", "xcd_map",
+                                                  "four_step_L1", "generic_passes")})
+    assert info["tune_candidates"] >= 4 and info["tune_ms"] > 0.0
+    a = base.apply(f)
+    b = tuned.apply(f)
+    ga = base.gradient(f)[1]
+    gb = tuned.gradient(f)[1]
+    torch.cuda.synchronize()
+    assert (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(a)).item() <= 2e-6
+    assert (torch.linalg.vector_norm(ga - gb) / torch.linalg.vector_norm(ga)).item() <= 2e-6
+    if info["pad_bytes"] == 256 and info["xcd_map"] == 1 and info["four_step_L1"] == 0 and not info["generic_passes"]:
+        assert torch.equal(a, b)
