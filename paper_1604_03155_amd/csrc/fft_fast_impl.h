@@ -148,39 +148,68 @@ __device__ __forceinline__ void compute_stage(cplx<R>* v, int t, const cplx<R>* 
     }
 }
 
-// outputs of stage s -> LDS, barrier, inputs of stage s+1 <- LDS, barrier
-template <typename R, int L, int C, int NT, int MODE, RP P, int s>
+// outputs of stage s -> LDS, barrier, inputs of stage s+1 <- LDS, barrier.
+// SPLIT: real parts first, then imaginary parts, through half the LDS.
+template <typename R, int L, int C, int NT, int MODE, RP P, int s, bool SPLIT>
 __device__ __forceinline__ void exchange(cplx<R>* v, cplx<R>* lds, int t) {
     using LY = Lay<L, C, MODE, (int)sizeof(cplx<R>)>;
     constexpr int RAD = P.r[s];
     constexpr int NS = ns_before(P, s);
     constexpr int E = C * L / NT;
-#pragma unroll
-    for (int i = 0; i < E / RAD; ++i) {
-        int q, j;
-        bmap<L, C, NT, MODE, RAD>(t, i, q, j);
-        const int ob = (j / NS) * NS * RAD + (j % NS);
-#pragma unroll
-        for (int r = 0; r < RAD; ++r) lds[LY::idx(q, ob + r * NS)] = v[i * RAD + r];
-    }
-    __syncthreads();
     constexpr int RN = P.r[s + 1];
+    if constexpr (SPLIT) {
+        R* lr = reinterpret_cast<R*>(lds);
 #pragma unroll
-    for (int i = 0; i < E / RN; ++i) {
-        int q, j;
-        bmap<L, C, NT, MODE, RN>(t, i, q, j);
+        for (int part = 0; part < 2; ++part) {
 #pragma unroll
-        for (int r = 0; r < RN; ++r) v[i * RN + r] = lds[LY::idx(q, j + r * (L / RN))];
+            for (int i = 0; i < E / RAD; ++i) {
+                int q, j;
+                bmap<L, C, NT, MODE, RAD>(t, i, q, j);
+                const int ob = (j / NS) * NS * RAD + (j % NS);
+#pragma unroll
+                for (int r = 0; r < RAD; ++r) lr[LY::idx(q, ob + r * NS)] = part ? v[i * RAD + r].y : v[i * RAD + r].x;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < E / RN; ++i) {
+                int q, j;
+                bmap<L, C, NT, MODE, RN>(t, i, q, j);
+#pragma unroll
+                for (int r = 0; r < RN; ++r) {
+                    const R x = lr[LY::idx(q, j + r * (L / RN))];
+                    if (part) v[i * RN + r].y = x;
+                    else v[i * RN + r].x = x;
+                }
+            }
+            __syncthreads();
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < E / RAD; ++i) {
+            int q, j;
+            bmap<L, C, NT, MODE, RAD>(t, i, q, j);
+            const int ob = (j / NS) * NS * RAD + (j % NS);
+#pragma unroll
+            for (int r = 0; r < RAD; ++r) lds[LY::idx(q, ob + r * NS)] = v[i * RAD + r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < E / RN; ++i) {
+            int q, j;
+            bmap<L, C, NT, MODE, RN>(t, i, q, j);
+#pragma unroll
+            for (int r = 0; r < RN; ++r) v[i * RN + r] = lds[LY::idx(q, j + r * (L / RN))];
+        }
+        __syncthreads();
     }
-    __syncthreads();
 }
 
-template <typename R, int L, int C, int NT, int MODE, int DIR, RP P, int s>
+template <typename R, int L, int C, int NT, int MODE, int DIR, RP P, int s, bool SPLIT = false>
 __device__ __forceinline__ void run_from(cplx<R>* v, cplx<R>* lds, int t, const cplx<R>* __restrict__ tw) {
     compute_stage<R, L, C, NT, MODE, DIR, P, s>(v, t, tw);
     if constexpr (s + 1 < P.n) {
-        exchange<R, L, C, NT, MODE, P, s>(v, lds, t);
-        run_from<R, L, C, NT, MODE, DIR, P, s + 1>(v, lds, t, tw);
+        exchange<R, L, C, NT, MODE, P, s, SPLIT>(v, lds, t);
+        run_from<R, L, C, NT, MODE, DIR, P, s + 1, SPLIT>(v, lds, t, tw);
     }
 }
 
@@ -443,23 +472,38 @@ struct KindIO {
 
 // Everything after the stage-0 loads of one tile: transforms, multiplies,
 // stores.  v holds the stage-0 inputs; kt the Khat values (fused kinds).
+// Per-kernel choices, all measured on the 3D N=256 apply (length 512):
+//  twl:   the twiddle table (L entries, at most 8 KiB) is copied to LDS once
+//         per workgroup; stage twiddles then come from LDS instead of the
+//         vector memory path (fused pass 0.47 -> 0.39 ms);
+//  split: the fused complex64 length-512 column pass exchanges real and
+//         imaginary parts in turn through half the LDS (32 instead of 64 KiB)
+//         and is held to 168 VGPRs, so 3 workgroups share a CU instead of 2
+//         (0.39 -> 0.36 ms).
+template <typename R, int L, int MODE, int FK>
+struct Policy {
+    static constexpr bool twl = L * (int)sizeof(cplx<R>) <= 8192 && make_plan(L, kMaxRad<R>).n >= 2;
+    static constexpr bool split = sizeof(R) == 4 && MODE == MODE_COL && FK == FK_FUSED && L == 512;
+    static constexpr int min_waves = split ? 3 : 1;
+};
+
 // FS: 0 plain pass; 1 four-step step A (forward, outputs times W^{o e});
 // 2 four-step step B (full-length forward, Khat at index o + L1 e, full-length
 // inverse, outputs times conj W^{o e}).
 template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX, int FS>
 __device__ __forceinline__ void tile_body(cplx<R>* v, cplx<R>* kt, cplx<R>* lds, const FTile& tl,
-                                          const PassDesc& p, int t) {
+                                          const PassDesc& p, int t, const cplx<R>* tw) {
     constexpr int NOUTI = FS == 2 ? L : L / 2;  // inverse outputs kept
     constexpr int PTI = FS == 2 ? 2 : 0;        // post twiddle of inverse outputs
     constexpr RP F = make_plan(L, kMaxRad<R>);
     constexpr RP I = reversed(F);
     constexpr int E = C * L / NT;
-    const cplx<R>* __restrict__ tw = reinterpret_cast<const cplx<R>*>(p.tw);
+    constexpr bool SP = Policy<R, L, MODE, FK>::split;
     cplx<R>* __restrict__ gout = reinterpret_cast<cplx<R>*>(p.out);
     cplx<R>* __restrict__ gout2 = reinterpret_cast<cplx<R>*>(p.out2);
     const R ks = (R)p.kscale;
     if constexpr (FK == FK_FWD) {
-        run_from<R, L, C, NT, MODE, -1, F, 0>(v, lds, t, tw);
+        run_from<R, L, C, NT, MODE, -1, F, 0, SP>(v, lds, t, tw);
         store_global<R, L, C, NT, MODE, F, L, FS == 1 ? 1 : 0>(v, gout, tl, p.out_se, t, p.tw_big);
     } else if constexpr (FK == FK_INV || FK == FK_INV_DERIV) {
         if constexpr (FK == FK_INV_DERIV) {
@@ -468,30 +512,30 @@ __device__ __forceinline__ void tile_body(cplx<R>* v, cplx<R>* kt, cplx<R>* lds,
 #pragma unroll
             for (int e = 0; e < E; ++e) v[e] = w[e];
         }
-        run_from<R, L, C, NT, MODE, +1, I, 0>(v, lds, t, tw);
+        run_from<R, L, C, NT, MODE, +1, I, 0, SP>(v, lds, t, tw);
         store_global<R, L, C, NT, MODE, I, L / 2>(v, gout, tl, p.out_se, t);
     } else if constexpr (FK == FK_INV_GRAD) {
         cplx<R> w[E];
         deriv_copy<R, L, C, NT, MODE, I.r[0]>(v, w, ks, t);
-        run_from<R, L, C, NT, MODE, +1, I, 0>(v, lds, t, tw);
+        run_from<R, L, C, NT, MODE, +1, I, 0, SP>(v, lds, t, tw);
         store_global<R, L, C, NT, MODE, I, L / 2>(v, gout, tl, p.out_se, t);
         __syncthreads();
-        run_from<R, L, C, NT, MODE, +1, I, 0>(w, lds, t, tw);
+        run_from<R, L, C, NT, MODE, +1, I, 0, SP>(w, lds, t, tw);
         store_global<R, L, C, NT, MODE, I, L / 2>(w, gout2, tl, p.out_se, t);
     } else {
-        run_from<R, L, C, NT, MODE, -1, F, 0>(v, lds, t, tw);
+        run_from<R, L, C, NT, MODE, -1, F, 0, SP>(v, lds, t, tw);
         table_apply<R, E, CPLX>(v, kt);
         if constexpr (FK == FK_FUSED) {
-            run_from<R, L, C, NT, MODE, +1, I, 0>(v, lds, t, tw);
+            run_from<R, L, C, NT, MODE, +1, I, 0, SP>(v, lds, t, tw);
             store_global<R, L, C, NT, MODE, I, NOUTI, PTI>(v, gout, tl, p.out_se, t, p.tw_big);
         } else {
             cplx<R> w[E];
             if constexpr (FS == 2) deriv_copy<R, L, C, NT, MODE, F.r[F.n - 1]>(v, w, ks, t, tl.o, p.fs_L1, p.L_big);
             else deriv_copy<R, L, C, NT, MODE, F.r[F.n - 1]>(v, w, ks, t);
-            run_from<R, L, C, NT, MODE, +1, I, 0>(v, lds, t, tw);
+            run_from<R, L, C, NT, MODE, +1, I, 0, SP>(v, lds, t, tw);
             store_global<R, L, C, NT, MODE, I, NOUTI, PTI>(v, gout, tl, p.out_se, t, p.tw_big);
             __syncthreads();
-            run_from<R, L, C, NT, MODE, +1, I, 0>(w, lds, t, tw);
+            run_from<R, L, C, NT, MODE, +1, I, 0, SP>(w, lds, t, tw);
             store_global<R, L, C, NT, MODE, I, NOUTI, PTI>(w, gout2, tl, p.out_se, t, p.tw_big);
         }
     }
@@ -500,6 +544,7 @@ __device__ __forceinline__ void tile_body(cplx<R>* v, cplx<R>* kt, cplx<R>* lds,
 // One tile (tile index b of the pass described by p).
 template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX, int FS>
 __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
+    using PO = Policy<R, L, MODE, FK>;
     constexpr RP F = make_plan(L, kMaxRad<R>);
     constexpr RP I = reversed(F);
     constexpr int E = C * L / NT;
@@ -507,7 +552,15 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
     constexpr RP PL = FL ? F : I;
     constexpr int NIN = (FL && FS != 2) ? L / 2 : L;
     using LY = Lay<L, C, MODE, (int)sizeof(cplx<R>)>;
-    __shared__ cplx<R> lds[LY::size];
+    __shared__ cplx<R> lds[PO::split ? (LY::size + 1) / 2 : LY::size];
+    __shared__ cplx<R> twl[PO::twl ? L : 1];
+    const cplx<R>* __restrict__ tw = reinterpret_cast<const cplx<R>*>(p.tw);
+    if constexpr (PO::twl) {
+        // copied once per workgroup; first read after the barrier of the
+        // first exchange (stage 0 of every plan runs without twiddles)
+        for (int i = threadIdx.x; i < L; i += NT) twl[i] = tw[i];
+        tw = twl;
+    }
     const int t = threadIdx.x;
     const FTile tl = fast_tile<C, MODE>(p, b);
     const cplx<R>* __restrict__ gin = reinterpret_cast<const cplx<R>*>(p.in);
@@ -520,12 +573,13 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
     else if constexpr (FK == FK_FUSED || FK == FK_FUSED_GRAD)
         table_fetch<R, L, C, NT, MODE, F, D, CPLX>(kt, p.table, p.tabN, tl.col0, tl.nvalid, t);
     expand<R, L, C, NT, PL, NIN>(v, vn);
-    tile_body<R, L, C, NT, MODE, FK, D, CPLX, FS>(v, kt, lds, tl, p, t);
+    tile_body<R, L, C, NT, MODE, FK, D, CPLX, FS>(v, kt, lds, tl, p, t, tw);
 }
 
 // One tile per workgroup.
 template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX, int FS>
-__global__ void __launch_bounds__(NT) fast_kernel(PassDesc p) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Policy<R, L, MODE, FK>::min_waves)))
+fast_kernel(PassDesc p) {
     fast_run<R, L, C, NT, MODE, FK, D, CPLX, FS>(p, p.xcd_map ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x);
 }
 
@@ -533,8 +587,8 @@ __global__ void __launch_bounds__(NT) fast_kernel(PassDesc p) {
 // descriptor each, same length and kind); item i owns the workgroups
 // [starts[i], starts[i + 1]).
 template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX, int FS>
-__global__ void __launch_bounds__(NT) fast_group_kernel(const PassDesc* __restrict__ descs,
-                                                       const unsigned* __restrict__ starts, int nitems) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Policy<R, L, MODE, FK>::min_waves)))
+fast_group_kernel(const PassDesc* __restrict__ descs, const unsigned* __restrict__ starts, int nitems) {
     const unsigned b = xcd_tile(blockIdx.x, gridDim.x);
     int i = 0;
     while (i + 1 < nitems && b >= starts[i + 1]) ++i;
