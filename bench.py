@@ -67,7 +67,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="helmholtz3d_k20_n256")
-    ap.add_argument("--cpu-sample", type=int, default=3, help="oracle applies timed for cpu_baseline (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=20,
+                    help="oracle applies timed for cpu_baseline (0: skip); 20 is about 10 s on 16 host threads")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--hbm-copy-mib", type=int, default=0,
                     help="after timing, run one streaming copy of this many MiB (counter calibration)")

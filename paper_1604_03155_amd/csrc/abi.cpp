@@ -10,6 +10,7 @@
 namespace vg {
 const char* last_error_cstr();
 vg_status precompute(vg_plan* p, hipStream_t s, bool keep_T);
+void finalize_bytes(vg_plan* p);
 vg_status batched_apply(int count, const vg_plan* const* plans, const void* const* f, void* const* phi,
                         void* workspace, hipStream_t stream);
 size_t batched_workspace_size(int count, const vg_plan* const* plans);
@@ -124,6 +125,7 @@ vg_status vg_plan_create_ex(int d, int N, vg_kernel kernel, double k, const vg_p
         if (st != VG_OK) return st;
         st = precompute(p.get(), s, o.keep_operator != 0);
         if (st != VG_OK) return st;
+        finalize_bytes(p.get());  // the fused passes' byte counts include the table, now sized
         st = autotune(p.get(), s);
         if (st != VG_OK) return st;
         *out = p.release();
