@@ -22,6 +22,18 @@ and the source, not from the closed forms):
   H_0 = H_0^(1).  The printed prefactor lacks the factor i and writes H_0(kr)
   inside the second integral; both are read as above (Graf's addition theorem
   averaged over circles gives exactly this).
+* 3D biharmonic (g = r/(8 pi)): u = [sigma sqrt(2/pi) e^{-a^2}
+  + erf(a)(sigma^2/r + r)] / (8 pi).  The printed formula lacks the factor
+  e^{-a^2} on the first term (it then exceeds the shell average by
+  sigma sqrt(2/pi)(1 - e^{-a^2})/(8 pi)); this is the reading used.
+* 2D biharmonic (g = -(r^2/(8 pi))(log r - 1)): u = -(sigma^2/(8 pi))
+  [(x + 1) Ein(x) - e^{-x}] + c_2 r^2 + c_1, x = r^2/(2 sigma^2),
+  Ein(x) = E_1(x) + log x + gamma, c_1, c_2 as printed.  The printed "Ei" is
+  read as E_1 (as for the 2D Laplace case) and the printed "c_1 r" as the
+  constant c_1 (its units are those of r^2; with these readings the formula
+  equals the circle-average integral below).
+* Delta (Delta + k^2) (g = g_k - g_0, the difference whose transform is the
+  tables' G_k - G_0): u = u_k - u_0.
 """
 from __future__ import annotations
 
@@ -148,17 +160,87 @@ def du_helmholtz2d(r, sigma, k):
     return np.asarray(out)
 
 
+# ---------------------------------------------------------- biharmonic ----
+
+def u_biharmonic3d(r, sigma):
+    r = np.asarray(r, dtype=np.float64)
+    a = r / (SQRT2 * sigma)
+    safe = np.where(r > 0, r, 1.0)
+    val = (sigma * math.sqrt(2.0 / math.pi) * np.exp(-a * a) + sp.erf(a) * (sigma * sigma / safe + r)) / (8 * math.pi)
+    # r -> 0: erf(a) sigma^2 / r -> sigma sqrt(2/pi) (1 - a^2/3), so
+    # u ~ [2 sigma sqrt(2/pi) + O(r^2)] / (8 pi)
+    u0 = 2.0 * sigma * math.sqrt(2.0 / math.pi) / (8 * math.pi)
+    return np.where(a < 1e-6, u0, val)
+
+
+def du_biharmonic3d(r, sigma):
+    """du/dr = [sqrt(2/pi) (sigma/r) e^{-a^2} + erf(a)(1 - sigma^2/r^2)] / (8 pi)."""
+    r = np.asarray(r, dtype=np.float64)
+    a = r / (SQRT2 * sigma)
+    safe = np.where(r > 0, r, 1.0)
+    val = (math.sqrt(2.0 / math.pi) * (sigma / safe) * np.exp(-a * a) + sp.erf(a) * (1.0 - sigma * sigma / safe ** 2)) / (8 * math.pi)
+    return np.where(a < 1e-4, 0.0, val)
+
+
+def _ein(x):
+    """Ein(x) = E_1(x) + log x + gamma = sum_{n>=1} (-1)^(n+1) x^n / (n n!)."""
+    x = np.asarray(x, dtype=np.float64)
+    safe = np.where(x > 0, x, 1.0)
+    big = sp.exp1(safe) + np.log(safe) + np.euler_gamma
+    ser = np.zeros_like(x)
+    for n in range(1, 40):
+        ser = ser + ((-1.0) ** (n + 1)) * x ** n / (n * math.factorial(n))
+    return np.where(x < 0.5, ser, big)
+
+
+def _bih2d_consts(sigma):
+    lg = math.log(1.0 / (2 * sigma * sigma))
+    c1 = sigma * sigma / (8 * math.pi) * (np.euler_gamma + lg)
+    c2 = (0.5 * np.euler_gamma + 0.5 * lg + 1.0) / (8 * math.pi)
+    return c1, c2
+
+
+def u_biharmonic2d(r, sigma):
+    r = np.asarray(r, dtype=np.float64)
+    x = r * r / (2 * sigma * sigma)
+    c1, c2 = _bih2d_consts(sigma)
+    return -(sigma * sigma / (8 * math.pi)) * ((x + 1.0) * _ein(x) - np.exp(-x)) + c2 * r * r + c1
+
+
+def du_biharmonic2d(r, sigma):
+    """du/dr = -(r/(8 pi)) [Ein(x) + 1 + (1 - e^{-x})/x] + 2 c_2 r, using
+    Ein'(x) = (1 - e^{-x})/x."""
+    r = np.asarray(r, dtype=np.float64)
+    x = r * r / (2 * sigma * sigma)
+    c1, c2 = _bih2d_consts(sigma)
+    safe = np.where(x > 0, x, 1.0)
+    q = np.where(x > 1e-8, -np.expm1(-safe) / safe, 1.0 - 0.5 * x)
+    return -(r / (8 * math.pi)) * (_ein(x) + 1.0 + q) + 2.0 * c2 * r
+
+
 # ------------------------------------------------------- sources on grids --
 
 def potential(d, kernel, k, r, sigma):
+    if kernel == "laplace_helmholtz":
+        return potential(d, "helmholtz", k, r, sigma) - potential(d, "laplace", k, r, sigma)
     if d == 3:
+        if kernel == "biharmonic":
+            return u_biharmonic3d(r, sigma).astype(np.complex128)
         return u_laplace3d(r, sigma).astype(np.complex128) if kernel == "laplace" else u_helmholtz3d(r, sigma, k)
+    if kernel == "biharmonic":
+        return u_biharmonic2d(r, sigma).astype(np.complex128)
     return u_laplace2d(r, sigma).astype(np.complex128) if kernel == "laplace" else u_helmholtz2d(r, sigma, k)
 
 
 def dpotential(d, kernel, k, r, sigma):
+    if kernel == "laplace_helmholtz":
+        return dpotential(d, "helmholtz", k, r, sigma) - dpotential(d, "laplace", k, r, sigma)
     if d == 3:
+        if kernel == "biharmonic":
+            return du_biharmonic3d(r, sigma).astype(np.complex128)
         return du_laplace3d(r, sigma).astype(np.complex128) if kernel == "laplace" else du_helmholtz3d(r, sigma, k)
+    if kernel == "biharmonic":
+        return du_biharmonic2d(r, sigma).astype(np.complex128)
     return du_laplace2d(r, sigma).astype(np.complex128) if kernel == "laplace" else du_helmholtz2d(r, sigma, k)
 
 
@@ -220,3 +302,41 @@ def shell_quadrature_2d_laplace(r, sigma):
     f = lambda t: -rho(t) * t * math.log(max(r, t)) if max(r, t) > 0 else 0.0
     pts = [r] if 0 < r < tmax else None
     return integrate.quad(f, 0, tmax, points=pts, limit=400, epsabs=1e-16, epsrel=1e-13)[0]
+
+
+def shell_quadrature_3d_biharmonic(r, sigma, derivative=False):
+    """u(r) (or du/dr) for g = r/(8 pi): the average of |x - y| over the sphere
+    |y| = t seen from |x| = r is r + t^2/(3r) for t < r and t + r^2/(3t) for
+    t > r (d/dr: 1 - t^2/(3r^2) and 2r/(3t))."""
+    rho = lambda t: (2 * math.pi * sigma ** 2) ** -1.5 * math.exp(-t * t / (2 * sigma * sigma))
+    if derivative:
+        avg = lambda t: (1.0 - t * t / (3 * r * r)) if t < r else 2.0 * r / (3.0 * t)
+    else:
+        avg = lambda t: (r + t * t / (3 * r)) if t < r else (t + r * r / (3 * t))
+    f = lambda t: rho(t) * 4 * math.pi * t * t * avg(t) / (8 * math.pi)
+    tmax = 40 * sigma
+    pts = [r] if 0 < r < tmax else None
+    return integrate.quad(f, 0, tmax, points=pts, limit=400, epsabs=1e-17, epsrel=1e-13)[0]
+
+
+def circle_quadrature_2d_biharmonic(r, sigma, derivative=False):
+    """u(r) (or du/dr) for g = -(R^2/(8 pi))(log R - 1), R = |x - y|: the circle
+    average of R^2 log R over |y| = t is r^2 log r + t^2 (log r + 1) for t < r
+    and t^2 log t + r^2 (log t + 1) for t > r (it solves the radial Poisson
+    equation with source 4 log max(r, t) + 4, the average of the Laplacian);
+    the average of R^2 is r^2 + t^2."""
+    rho = lambda t: math.exp(-t * t / (2 * sigma * sigma)) / (2 * math.pi * sigma * sigma)
+
+    def avg(t):
+        if derivative:
+            return (-(2 * r * math.log(r) - r + t * t / r) if t < r else -(2 * r * math.log(t))) / (8 * math.pi)
+        if t < r:
+            M = r * r * math.log(r) + t * t * (math.log(r) + 1.0)
+        else:
+            M = t * t * math.log(t) + r * r * (math.log(t) + 1.0)
+        return -(M - (r * r + t * t)) / (8 * math.pi)
+
+    f = lambda t: rho(t) * 2 * math.pi * t * avg(t) if t > 0 else 0.0
+    tmax = 40 * sigma
+    pts = [r] if 0 < r < tmax else None
+    return integrate.quad(f, 0, tmax, points=pts, limit=400, epsabs=1e-17, epsrel=1e-13)[0]

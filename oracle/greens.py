@@ -183,18 +183,83 @@ def g_helmholtz2d(s, k, L=1.5):
     return out
 
 
+def g_biharmonic3d(s, L=1.8):
+    """Table 1, operator Delta^2, kernel r/(8 pi):
+        G(s) = [(2 - x^2) cos x + 2 x sin x - 2] / (2 s^4),  x = L s.
+    The radial integral is G = (1/(2s)) int_0^L r^2 sin(s r) dr; expanding
+    sin(s r) and integrating term by term gives, for x < 1 (where the printed
+    numerator cancels to O(x^4)),
+        G = (L^4/2) sum_n (-1)^n x^(2n) / ((2n + 4) (2n + 1)!)   (G(0) = L^4/8)."""
+    s = np.asarray(s, dtype=np.float64)
+    x = L * s
+    out = np.empty(s.shape)
+    small = x < 1.0
+    if np.any(small):
+        xs = x[small]
+        acc = np.zeros_like(xs)
+        for n in range(14):
+            acc += ((-1.0) ** n) * xs ** (2 * n) / ((2 * n + 4) * math.factorial(2 * n + 1))
+        out[small] = 0.5 * L ** 4 * acc
+    big = ~small
+    if np.any(big):
+        sb, xb = s[big], x[big]
+        out[big] = ((2.0 - xb * xb) * np.cos(xb) + 2.0 * xb * np.sin(xb) - 2.0) / (2.0 * sb ** 4)
+    return out
+
+
+def g_biharmonic2d(s, L=1.5):
+    """Table 2, operator Delta^2, kernel -(r^2/(8 pi))(log r - 1):
+        G(s) = (J_0(x) - 1)/s^4 - L^3 (log L - 1) J_1(x)/(4 s)
+               + L log L J_1(x)/s^3 - L^2 (2 log L - 1) J_0(x)/(4 s^2),  x = L s.
+    The radial integral is G = -(1/4) int_0^L r^3 (log r - 1) J_0(s r) dr; with
+    the power series of J_0 and int_0^L r^m (log r - 1) dr =
+    L^(m+1) [(log L - 1)/(m+1) - 1/(m+1)^2], for x < 1 (where the printed terms
+    cancel from O(s^-4) to O(1))
+        G = -(L^4/4) sum_n (-1)^n (x/2)^(2n)/(n!)^2 [(log L - 1)/(2n+4) - 1/(2n+4)^2]."""
+    s = np.asarray(s, dtype=np.float64)
+    x = L * s
+    lg = math.log(L)
+    out = np.empty(s.shape)
+    small = x < 1.0
+    if np.any(small):
+        xs = x[small]
+        acc = np.zeros_like(xs)
+        for n in range(16):
+            m1 = 2 * n + 4
+            acc += ((-1.0) ** n) * (0.5 * xs) ** (2 * n) / math.factorial(n) ** 2 * ((lg - 1.0) / m1 - 1.0 / m1 ** 2)
+        out[small] = -0.25 * L ** 4 * acc
+    big = ~small
+    if np.any(big):
+        sb, xb = s[big], x[big]
+        J0, J1 = sp.j0(xb), sp.j1(xb)
+        out[big] = ((J0 - 1.0) / sb ** 4 - L ** 3 * (lg - 1.0) * J1 / (4.0 * sb) + L * lg * J1 / sb ** 3
+                    - L * L * (2.0 * lg - 1.0) * J0 / (4.0 * sb * sb))
+    return out
+
+
+KERNELS = ("laplace", "helmholtz", "biharmonic", "laplace_helmholtz")
+
+
 def kernel_transform(d, kernel, s, k=0.0, L=None):
-    """Dispatch G^L(s) for d in {2, 3} and kernel in {'laplace', 'helmholtz'}."""
+    """Dispatch G^L(s) for d in {2, 3} and the kernels of Tables 1-2:
+    'laplace' (Delta), 'helmholtz' (Delta + k^2), 'biharmonic' (Delta^2) and
+    'laplace_helmholtz' (Delta (Delta + k^2), G = G_k - G_0 as in both tables)."""
     if L is None:
         L = L_DEFAULT[d]
     if d == 3 and kernel == "laplace":
         return g_laplace3d(s, L).astype(np.complex128)
     if d == 3 and kernel == "helmholtz":
         return g_helmholtz3d(s, k, L)
+    if d == 3 and kernel == "biharmonic":
+        return g_biharmonic3d(s, L).astype(np.complex128)
     if d == 2 and kernel == "laplace":
         return g_laplace2d(s, L).astype(np.complex128)
     if d == 2 and kernel == "helmholtz":
         return g_helmholtz2d(s, k, L)
+    if d == 2 and kernel == "biharmonic":
+        return g_biharmonic2d(s, L).astype(np.complex128)
+    if kernel == "laplace_helmholtz":
+        return kernel_transform(d, "helmholtz", s, k, L) - kernel_transform(d, "laplace", s, k, L)
     raise ValueError(f"unsupported d={d} kernel={kernel}")
 
 
@@ -213,6 +278,16 @@ def radial_quadrature(d, kernel, s, k=0.0, L=None, points=None):
     if L is None:
         L = L_DEFAULT[d]
     s = float(s)
+    if kernel == "laplace_helmholtz":
+        return (radial_quadrature(d, "helmholtz", s, k, L, points)
+                - radial_quadrature(d, "laplace", s, k, L, points))
+    if kernel == "biharmonic":
+        # 3D: g = r/(8 pi): (1/s) int_0^L sin(s r) (r/(8 pi)) 4 pi r dr; 2D: 2 pi int_0^L J_0(s r) g(r) r dr
+        if d == 3:
+            f = (lambda r: 0.5 * r ** 3) if s == 0.0 else (lambda r: 0.5 * r * r * math.sin(s * r) / s)
+        else:
+            f = lambda r: -0.25 * r ** 3 * (math.log(r) - 1.0) * sp.j0(s * r) if r > 0 else 0.0
+        return complex(integrate.quad(f, 0.0, L, limit=400, epsabs=1e-15, epsrel=1e-14, points=points)[0], 0.0)
     if d == 3:
         if s == 0.0:
             fr = lambda r: r * math.cos(k * r)

@@ -21,6 +21,10 @@ CASES = [
     (2, "laplace", 0.0),
     (2, "helmholtz", 2.0),
     (2, "helmholtz", 200.0),
+    (3, "biharmonic", 0.0),
+    (2, "biharmonic", 0.0),
+    (3, "laplace_helmholtz", 7.0),
+    (2, "laplace_helmholtz", 30.0),
 ]
 
 
@@ -115,3 +119,35 @@ def test_truncated_spectrum_tends_to_free_space_spectrum():
     k = 4.0
     hel = g.g_helmholtz3d(s, k)
     assert np.mean((hel * (s * s - k * k)).real) == pytest.approx(1.0, abs=0.05)
+
+
+def test_biharmonic_printed_forms_limits_and_series_crossover():
+    """Table 1 and Table 2 biharmonic transforms as printed (away from s = 0),
+    their s = 0 values (3D: L^4/8; 2D: -(L^4/4)[(log L - 1)/4 - 1/16]) and
+    continuity where the oracle switches from the series to the printed form
+    (L s = 1)."""
+    L3, L2 = 1.8, 1.5
+    s = np.array([0.7, 2.0, 9.0, 40.0])
+    x = L3 * s
+    printed3 = ((2 - x * x) * np.cos(x) + 2 * x * np.sin(x) - 2) / (2 * s ** 4)
+    assert np.allclose(g.g_biharmonic3d(s, L3), printed3, rtol=1e-12, atol=0)
+    x = L2 * s
+    lg = math.log(L2)
+    printed2 = ((sp.j0(x) - 1) / s ** 4 - L2 ** 3 * (lg - 1) * sp.j1(x) / (4 * s) + L2 * lg * sp.j1(x) / s ** 3
+                - L2 ** 2 * (2 * lg - 1) * sp.j0(x) / (4 * s * s))
+    assert np.allclose(g.g_biharmonic2d(s, L2), printed2, rtol=1e-12, atol=0)
+    assert g.g_biharmonic3d(np.array([0.0]), L3)[0] == pytest.approx(L3 ** 4 / 8, rel=1e-15)
+    assert g.g_biharmonic2d(np.array([0.0]), L2)[0] == pytest.approx(-(L2 ** 4 / 4) * ((lg - 1) / 4 - 1 / 16), rel=1e-15)
+    for L, fn in ((L3, g.g_biharmonic3d), (L2, g.g_biharmonic2d)):
+        a, b = fn(np.array([(1 - 1e-14) / L, (1 + 1e-14) / L]), L)
+        assert abs(a - b) <= 1e-13 * abs(a)
+
+
+def test_laplace_helmholtz_is_difference_and_vanishes_as_k_to_0():
+    """Delta(Delta + k^2): both tables give G_k - G_0; in 3D it tends to 0 with k."""
+    s = np.linspace(0, 40, 81)
+    for d in (2, 3):
+        diff = g.kernel_transform(d, "helmholtz", s, 9.0) - g.kernel_transform(d, "laplace", s, 0.0)
+        assert np.array_equal(g.kernel_transform(d, "laplace_helmholtz", s, 9.0), diff)
+    small = g.kernel_transform(3, "laplace_helmholtz", s, 1e-4)
+    assert np.max(np.abs(small)) < 1e-3

@@ -35,7 +35,9 @@ def _random_density(rng, d, N, margin=0, real=False):
 
 
 @pytest.mark.parametrize("d,N,kernel,k", [(3, 4, "helmholtz", 3.0), (3, 4, "laplace", 0.0),
-                                          (2, 8, "helmholtz", 5.0), (2, 6, "laplace", 0.0)])
+                                          (2, 8, "helmholtz", 5.0), (2, 6, "laplace", 0.0),
+                                          (3, 4, "biharmonic", 0.0), (2, 8, "biharmonic", 0.0),
+                                          (3, 4, "laplace_helmholtz", 4.0), (2, 6, "laplace_helmholtz", 9.0)])
 def test_T_equals_naive_lattice_sum(d, N, kernel, k):
     """Eq. (1) of the operator module by brute force: M^-d sum_m G e^{2 pi i m.n/M}."""
     plan = op.Plan(d, N, kernel, k, route="full")
@@ -52,7 +54,9 @@ def test_T_equals_naive_lattice_sum(d, N, kernel, k):
 
 
 @pytest.mark.parametrize("d,N,kernel,k", [(3, 12, "helmholtz", 7.0), (2, 20, "laplace", 0.0),
-                                          (2, 16, "helmholtz", 30.0), (3, 10, "laplace", 0.0)])
+                                          (2, 16, "helmholtz", 30.0), (3, 10, "laplace", 0.0),
+                                          (3, 10, "biharmonic", 0.0), (2, 16, "biharmonic", 0.0),
+                                          (2, 16, "laplace_helmholtz", 12.0)])
 def test_octant_route_equals_full_lattice_route(d, N, kernel, k):
     full = op.Plan(d, N, kernel, k, route="full")
     octa = op.Plan(d, N, kernel, k, route="octant")
@@ -115,7 +119,8 @@ def test_2n_route_equals_4n_route(d, N, kernel, k):
 
 
 @pytest.mark.parametrize("d,N,kernel,k", [(3, 6, "helmholtz", 5.0), (2, 10, "laplace", 0.0),
-                                          (2, 8, "helmholtz", 12.0)])
+                                          (2, 8, "helmholtz", 12.0), (3, 6, "biharmonic", 0.0),
+                                          (2, 10, "laplace_helmholtz", 7.0)])
 def test_apply_equals_direct_summation(d, N, kernel, k):
     rng = np.random.default_rng(2)
     plan = op.Plan(d, N, kernel, k)
@@ -151,6 +156,10 @@ CONVERGENCE = [
     (3, "helmholtz", 2.0, 24, 3e-6), (3, "helmholtz", 2.0, 48, 1e-14),
     (2, "laplace", 0.0, 32, 2e-8), (2, "laplace", 0.0, 64, 1e-14),
     (2, "helmholtz", 2.0, 32, 3e-8), (2, "helmholtz", 2.0, 64, 1e-14),
+    # the other kernels of Tables 1-2 (Delta^2 and Delta(Delta + k^2))
+    (3, "biharmonic", 0.0, 24, 2e-5), (3, "biharmonic", 0.0, 48, 1e-14),
+    (2, "biharmonic", 0.0, 32, 1e-7), (2, "biharmonic", 0.0, 64, 1e-14),
+    (3, "laplace_helmholtz", 2.0, 48, 1e-14), (2, "laplace_helmholtz", 20.0, 64, 1e-14),
 ]
 
 
@@ -159,11 +168,11 @@ def test_gaussian_source_converges_spectrally_to_closed_form(d, kernel, k, N, bo
     sigma = 0.05
     r, f = _centered_gaussian(d, N, sigma)
     phi = op.Plan(d, N, kernel, k).apply(f)
-    if d == 2 and kernel == "helmholtz":
+    if d == 2 and kernel in ("helmholtz", "laplace_helmholtz"):
         rng = np.random.default_rng(5)
         idx = rng.integers(0, N, size=(12, d))
         rr = r[tuple(idx.T)]
-        ref = cf.u_helmholtz2d(rr, sigma, k)
+        ref = cf.potential(d, kernel, k, rr, sigma)
         err = np.max(np.abs(phi[tuple(idx.T)] - ref)) / np.max(np.abs(ref))
     else:
         ref = cf.potential(d, kernel, k, r.ravel(), sigma).reshape(r.shape)
@@ -190,14 +199,19 @@ def test_offcentre_gaussian_sum_matches_closed_form():
 
 
 @pytest.mark.parametrize("d,kernel,k,N", [(3, "laplace", 0.0, 48), (3, "helmholtz", 2.0, 48),
-                                          (2, "laplace", 0.0, 64), (2, "helmholtz", 20.0, 64)])
+                                          (2, "laplace", 0.0, 64), (2, "helmholtz", 20.0, 64),
+                                          (3, "biharmonic", 0.0, 48), (2, "biharmonic", 0.0, 64),
+                                          (3, "laplace_helmholtz", 2.0, 48)])
 def test_gradient_routes_agree_and_match_closed_form(d, kernel, k, N):
     sigma = 0.05
     r, f = _centered_gaussian(d, N, sigma)
     plan = op.Plan(d, N, kernel, k)
     gB = plan.gradient(f)
     gA = op.gradient_4n(f, plan.Ghat)
-    assert np.linalg.norm(gA - gB) / np.linalg.norm(gA) < 2e-13
+    # biharmonic entries grow like |n| h, and G_k - G_0 cancels to k^2/s^4 out
+    # of two 1/s^2 terms at large s, so these two carry more rounding
+    loose = kernel in ("biharmonic", "laplace_helmholtz")
+    assert np.linalg.norm(gA - gB) / np.linalg.norm(gA) < (2e-12 if loose else 2e-13)
     x = grid_coords(N)
     X = np.meshgrid(*([x] * d), indexing="ij")
     pts = np.stack([xx.ravel() for xx in X], 1)
@@ -208,16 +222,27 @@ def test_gradient_routes_agree_and_match_closed_form(d, kernel, k, N):
 
 
 @pytest.mark.parametrize("d,kernel,k,N", [(3, "laplace", 0.0, 48), (3, "helmholtz", 2.0, 48),
-                                          (2, "helmholtz", 20.0, 64)])
+                                          (2, "helmholtz", 20.0, 64), (3, "biharmonic", 0.0, 48),
+                                          (2, "biharmonic", 0.0, 64), (3, "laplace_helmholtz", 3.0, 48)])
 def test_pde_residual_on_the_box(d, kernel, k, N):
     """phi = g * f solves (Delta + k^2) phi = -f (the sign follows from
-    phi = g * f with the outgoing kernel); evaluated spectrally on the
-    uncropped 2N-periodic potential and restricted to the box."""
+    phi = g * f with the outgoing kernel), Delta^2 phi = -f for the biharmonic
+    kernel and Delta (Delta + k^2) phi = k^2 f for the tables' g_k - g_0;
+    evaluated spectrally on the uncropped 2N-periodic potential and restricted
+    to the box."""
     sigma = 0.05
     _, f = _centered_gaussian(d, N, sigma)
     plan = op.Plan(d, N, kernel, k)
     spec = plan.Khat * op.fftn(op.pad(f, 2 * N))
     kap = math.pi * op.signed_index(2 * N)
     K2 = sum((kap ** 2).reshape([-1 if a == b else 1 for b in range(d)]) for a in range(d))
-    res = op.crop(op.ifftn((k * k - K2) * spec), N) + f
-    assert np.linalg.norm(res) / np.linalg.norm(f) < 1e-12
+    if kernel == "biharmonic":
+        res = op.crop(op.ifftn(K2 * K2 * spec), N) + f
+    elif kernel == "laplace_helmholtz":
+        res = op.crop(op.ifftn(-K2 * (k * k - K2) * spec), N) - k * k * f
+    else:
+        res = op.crop(op.ifftn((k * k - K2) * spec), N) + f
+    # the fourth-order operators amplify rounding at the top frequencies by
+    # |kappa|^4 ~ 5e9 (N = 48); a wrong sign or factor leaves an O(1) residual
+    bound = 1e-8 if kernel in ("biharmonic", "laplace_helmholtz") else 1e-12
+    assert np.linalg.norm(res) / np.linalg.norm(f) < bound
