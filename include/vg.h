@@ -59,9 +59,14 @@ typedef enum vg_status {
     VG_ERR_INTERNAL = 7          /* a bug: please report */
 } vg_status;
 
+/* The kernels of Tables 1 (3D) and 2 (2D), with the tables' Green's functions
+ * (each satisfies L g = -delta for its operator L, except the last, whose
+ * tabulated g_k - g_0 satisfies Delta(Delta + k^2) g = k^2 delta). */
 typedef enum vg_kernel {
-    VG_LAPLACE = 0,   /* Delta:        1/(4 pi r) (3D),  -(1/2 pi) log r (2D) */
-    VG_HELMHOLTZ = 1  /* Delta + k^2:  e^{ikr}/(4 pi r) (3D), (i/4) H_0^(1)(kr) (2D) */
+    VG_LAPLACE = 0,           /* Delta:        1/(4 pi r) (3D),  -(1/2 pi) log r (2D) */
+    VG_HELMHOLTZ = 1,         /* Delta + k^2:  e^{ikr}/(4 pi r) (3D), (i/4) H_0^(1)(kr) (2D) */
+    VG_BIHARMONIC = 2,        /* Delta^2:      r/(8 pi) (3D), -(r^2/(8 pi))(log r - 1) (2D) */
+    VG_LAPLACE_HELMHOLTZ = 3  /* Delta (Delta + k^2): g_k - g_0, the difference of the two above */
 } vg_kernel;
 
 typedef enum vg_precision {
@@ -114,8 +119,8 @@ typedef struct vg_plan_info {
 } vg_plan_info;
 
 /*
- * Create a plan for d in {2, 3}, even N >= 4, kernel in {VG_LAPLACE,
- * VG_HELMHOLTZ}.  Helmholtz needs a finite k > 0 (Laplace ignores k).
+ * Create a plan for d in {2, 3}, even N >= 4 and a vg_kernel.  VG_HELMHOLTZ
+ * and VG_LAPLACE_HELMHOLTZ need a finite k > 0 (the others ignore k).
  * Runs the FP64 precompute of Sections 2 and 4 on the current device and
  * synchronises before returning.
  * Errors: VG_ERR_INVALID_ARG (bad arguments; *out untouched),

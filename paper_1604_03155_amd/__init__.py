@@ -23,10 +23,10 @@ __all__ = [
 
 LIBRARY_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvgconv.so")
 
-LAPLACE, HELMHOLTZ = 0, 1
+LAPLACE, HELMHOLTZ, BIHARMONIC, LAPLACE_HELMHOLTZ = 0, 1, 2, 3
 FP32, FP64 = 0, 1
 _TUNE = {"off": 0, "quick": 1, "full": 2}
-_KERNELS = {"laplace": LAPLACE, "helmholtz": HELMHOLTZ}
+_KERNELS = {"laplace": LAPLACE, "helmholtz": HELMHOLTZ, "biharmonic": BIHARMONIC, "laplace_helmholtz": LAPLACE_HELMHOLTZ}
 
 if not os.path.exists(LIBRARY_PATH):
     raise ImportError(f"{LIBRARY_PATH} is missing: build it with `python -m paper_1604_03155_amd.build`")
@@ -115,8 +115,9 @@ def _stream_ptr(stream):
 class Plan:
     """A precomputed truncated-kernel convolution operator for one grid.
 
-    d: 2 or 3; N: even points per side (h = 1/N); kernel: 'laplace' or
-    'helmholtz' (wavenumber k > 0); precision: 'fp32' (complex64 data, tables
+    d: 2 or 3; N: even points per side (h = 1/N); kernel: 'laplace',
+    'helmholtz' (wavenumber k > 0), 'biharmonic' or 'laplace_helmholtz'
+    (Delta (Delta + k^2), kernel g_k - g_0, k > 0) (Tables 1-2); precision: 'fp32' (complex64 data, tables
     built in FP64 and rounded once) or 'fp64'.  L and P default to the paper's
     truncation radius (1.8 in 3D, 1.5 in 2D) and 4-fold oversampling."""
 

@@ -83,8 +83,10 @@ vg_status vg_plan_create_ex(int d, int N, vg_kernel kernel, double k, const vg_p
         *out = nullptr;
         if (d != 2 && d != 3) return fail(VG_ERR_INVALID_ARG, "d must be 2 or 3");
         if (N < 4 || (N % 2)) return fail(VG_ERR_INVALID_ARG, "N must be even and at least 4");
-        if (kernel != VG_LAPLACE && kernel != VG_HELMHOLTZ) return fail(VG_ERR_INVALID_ARG, "unknown kernel");
-        if (kernel == VG_HELMHOLTZ && !(std::isfinite(k) && k > 0.0))
+        if (kernel != VG_LAPLACE && kernel != VG_HELMHOLTZ && kernel != VG_BIHARMONIC && kernel != VG_LAPLACE_HELMHOLTZ)
+            return fail(VG_ERR_INVALID_ARG, "unknown kernel");
+        const bool helm = kernel == VG_HELMHOLTZ || kernel == VG_LAPLACE_HELMHOLTZ;
+        if (helm && !(std::isfinite(k) && k > 0.0))
             return fail(VG_ERR_INVALID_ARG, "Helmholtz needs a finite k > 0");
         vg_plan_opts o;
         std::memset(&o, 0, sizeof(o));
@@ -110,14 +112,14 @@ vg_status vg_plan_create_ex(int d, int N, vg_kernel kernel, double k, const vg_p
         p->d = d;
         p->N = N;
         p->kernel = kernel;
-        p->k = (kernel == VG_HELMHOLTZ) ? k : 0.0;
+        p->k = helm ? k : 0.0;
         p->L = L;
         p->P = P;
         p->precision = o.precision;
         p->fp64 = o.precision == VG_FP64;
         p->tune = o.tune;
         p->radices = rad;
-        p->table_complex = (kernel == VG_HELMHOLTZ) ? 1 : 0;
+        p->table_complex = helm ? 1 : 0;
         hipError_t he = hipGetDevice(&p->device);
         if (he != hipSuccess) return from_hip(he, "hipGetDevice");
         hipStream_t s = reinterpret_cast<hipStream_t>(o.stream);

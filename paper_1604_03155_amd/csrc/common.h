@@ -56,6 +56,7 @@ enum PassKind : int {
     KIND_FUSED = 2,      // forward, multiply by the Khat octant, inverse
     KIND_FUSED_GRAD = 3, // as FUSED, second output multiplied by i*kappa along this axis
     KIND_INV_GRAD = 4,   // inverse to out, and inverse of (i*kappa * in) to out2
+    KIND_FUSED_DERIV = 5,  // forward, multiply by the Khat octant and i*kappa, inverse
 };
 
 constexpr int kMaxStages = 12;
@@ -102,7 +103,7 @@ struct PassDesc {
 // ----------------------------------------------------- plan precompute ----
 struct GreensParams {
     int d;
-    int kernel;      // 0 Laplace, 1 Helmholtz
+    int kernel;      // vg_kernel: 0 Laplace, 1 Helmholtz, 2 biharmonic, 3 Delta (Delta + k^2)
     double k, L;
     double ds;       // lattice spacing 2 pi / P
     // 2D Helmholtz constants H_0^(1)(kL), H_1^(1)(kL) and Taylor

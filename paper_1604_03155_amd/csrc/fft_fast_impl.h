@@ -21,6 +21,8 @@
 // on the same XCD and share its L2 and TLB.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 #include "butterfly.h"
 
@@ -461,13 +463,21 @@ __device__ __forceinline__ void deriv_copy(const cplx<R>* v, cplx<R>* v2, R ks, 
     }
 }
 
-enum FastKind : int { FK_FWD = 0, FK_INV = 1, FK_FUSED = 2, FK_FUSED_GRAD = 3, FK_INV_GRAD = 4, FK_INV_DERIV = 5 };
+enum FastKind : int {
+    FK_FWD = 0,
+    FK_INV = 1,
+    FK_FUSED = 2,
+    FK_FUSED_GRAD = 3,
+    FK_INV_GRAD = 4,
+    FK_INV_DERIV = 5,
+    FK_FUSED_DERIV = 6
+};
 
 template <int FK>
 struct KindIO {
     // forward kinds load zero-padded pencils with the forward plan; inverse
     // kinds load full spectral pencils with the reversed plan
-    static constexpr bool fwd_load = FK == FK_FWD || FK == FK_FUSED || FK == FK_FUSED_GRAD;
+    static constexpr bool fwd_load = FK == FK_FWD || FK == FK_FUSED || FK == FK_FUSED_GRAD || FK == FK_FUSED_DERIV;
 };
 
 // Everything after the stage-0 loads of one tile: transforms, multiplies,
@@ -476,14 +486,16 @@ struct KindIO {
 //  twl:   the twiddle table (L entries, at most 8 KiB) is copied to LDS once
 //         per workgroup; stage twiddles then come from LDS instead of the
 //         vector memory path (fused pass 0.47 -> 0.39 ms);
-//  split: the fused complex64 length-512 column pass exchanges real and
-//         imaginary parts in turn through half the LDS (32 instead of 64 KiB)
-//         and is held to 168 VGPRs, so 3 workgroups share a CU instead of 2
-//         (0.39 -> 0.36 ms).
+//  split: the fused complex64 length-512 and length-1024 column passes
+//         exchange real and imaginary parts in turn through half the LDS (32
+//         instead of 64 KiB) and are held to 168 VGPRs, so 3 workgroups share
+//         a CU instead of 2 (length 512 at N = 256: 0.39 -> 0.34 ms; length
+//         1024 at N = 512: 3.61 -> 3.47 ms).
 template <typename R, int L, int MODE, int FK>
 struct Policy {
     static constexpr bool twl = L * (int)sizeof(cplx<R>) <= 8192 && make_plan(L, kMaxRad<R>).n >= 2;
-    static constexpr bool split = sizeof(R) == 4 && MODE == MODE_COL && FK == FK_FUSED && L == 512;
+    static constexpr bool split =
+        sizeof(R) == 4 && MODE == MODE_COL && (FK == FK_FUSED || FK == FK_FUSED_DERIV) && (L == 512 || L == 1024);
     static constexpr int min_waves = split ? 3 : 1;
 };
 
@@ -525,7 +537,11 @@ __device__ __forceinline__ void tile_body(cplx<R>* v, cplx<R>* kt, cplx<R>* lds,
     } else {
         run_from<R, L, C, NT, MODE, -1, F, 0, SP>(v, lds, t, tw);
         table_apply<R, E, CPLX>(v, kt);
-        if constexpr (FK == FK_FUSED) {
+        if constexpr (FK == FK_FUSED_DERIV) {
+            if constexpr (FS == 2) deriv_copy<R, L, C, NT, MODE, F.r[F.n - 1]>(v, v, ks, t, tl.o, p.fs_L1, p.L_big);
+            else deriv_copy<R, L, C, NT, MODE, F.r[F.n - 1]>(v, v, ks, t);
+        }
+        if constexpr (FK == FK_FUSED || FK == FK_FUSED_DERIV) {
             run_from<R, L, C, NT, MODE, +1, I, 0, SP>(v, lds, t, tw);
             store_global<R, L, C, NT, MODE, I, NOUTI, PTI>(v, gout, tl, p.out_se, t, p.tw_big);
         } else {
@@ -566,11 +582,12 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
     const cplx<R>* __restrict__ gin = reinterpret_cast<const cplx<R>*>(p.in);
     cplx<R> vn[LoadSet<R, L, C, NT, PL, NIN>::NV];
     cplx<R> v[E];
-    cplx<R> kt[(FK == FK_FUSED || FK == FK_FUSED_GRAD) ? E : 1];
+    constexpr bool TAB = FK == FK_FUSED || FK == FK_FUSED_GRAD || FK == FK_FUSED_DERIV;
+    cplx<R> kt[TAB ? E : 1];
     issue_loads<R, L, C, NT, MODE, PL, NIN>(vn, gin, tl, p.in_se, t);
-    if constexpr ((FK == FK_FUSED || FK == FK_FUSED_GRAD) && FS == 2)
+    if constexpr (TAB && FS == 2)
         table_fetch_fs<R, L, C, NT, MODE, F, CPLX>(kt, p.table, p.tabN, tl.col0, tl.nvalid, tl.o, p.fs_L1, p.L_big, t);
-    else if constexpr (FK == FK_FUSED || FK == FK_FUSED_GRAD)
+    else if constexpr (TAB)
         table_fetch<R, L, C, NT, MODE, F, D, CPLX>(kt, p.table, p.tabN, tl.col0, tl.nvalid, t);
     expand<R, L, C, NT, PL, NIN>(v, vn);
     tile_body<R, L, C, NT, MODE, FK, D, CPLX, FS>(v, kt, lds, tl, p, t, tw);
@@ -613,31 +630,31 @@ hipError_t launch_shape(const PassDesc& p, int kind, hipStream_t s, const GroupA
                               : (MODE == MODE_COL ? (long long)p.outer * ((p.inner + C - 1) / C) : (p.outer + C - 1) / C);
     if (nblocks <= 0) return hipSuccess;
     if (nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    const bool fused = kind == KIND_FUSED || kind == KIND_FUSED_GRAD;
+    const bool fused = kind == KIND_FUSED || kind == KIND_FUSED_GRAD || kind == KIND_FUSED_DERIV;
     if constexpr (MODE == MODE_ROW) {
         if (fused) return hipErrorInvalidValue;  // fused passes are column passes
-    } else if (fused && p.fs_L1) {
-        // four-step step B (2D only)
-        const bool g = kind == KIND_FUSED_GRAD;
-        if (p.d != 2 || p.post_tw != 2) return hipErrorInvalidValue;
-        if (p.table_complex)
-            return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 2, true, 2, GROUP>(p, nblocks, s, ga)
-                     : launch_k<R, L, C, NT, MODE, FK_FUSED, 2, true, 2, GROUP>(p, nblocks, s, ga);
-        return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 2, false, 2, GROUP>(p, nblocks, s, ga)
-                 : launch_k<R, L, C, NT, MODE, FK_FUSED, 2, false, 2, GROUP>(p, nblocks, s, ga);
     } else if (fused) {
-        const bool g = kind == KIND_FUSED_GRAD;
-        if (p.d == 3 && p.table_complex)
-            return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 3, true, 0, GROUP>(p, nblocks, s, ga)
-                     : launch_k<R, L, C, NT, MODE, FK_FUSED, 3, true, 0, GROUP>(p, nblocks, s, ga);
-        if (p.d == 3)
-            return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 3, false, 0, GROUP>(p, nblocks, s, ga)
-                     : launch_k<R, L, C, NT, MODE, FK_FUSED, 3, false, 0, GROUP>(p, nblocks, s, ga);
-        if (p.table_complex)
-            return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 2, true, 0, GROUP>(p, nblocks, s, ga)
-                     : launch_k<R, L, C, NT, MODE, FK_FUSED, 2, true, 0, GROUP>(p, nblocks, s, ga);
-        return g ? launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, 2, false, 0, GROUP>(p, nblocks, s, ga)
-                 : launch_k<R, L, C, NT, MODE, FK_FUSED, 2, false, 0, GROUP>(p, nblocks, s, ga);
+        // D (table dimension), CPLX (table type) and FS (four-step step B) are compile-time
+        auto by_kind = [&](auto dc, auto cc, auto fc) -> hipError_t {
+            constexpr int DD = decltype(dc)::value;
+            constexpr bool CC = decltype(cc)::value;
+            constexpr int FF = decltype(fc)::value;
+            if (kind == KIND_FUSED_GRAD) return launch_k<R, L, C, NT, MODE, FK_FUSED_GRAD, DD, CC, FF, GROUP>(p, nblocks, s, ga);
+            if (kind == KIND_FUSED_DERIV) return launch_k<R, L, C, NT, MODE, FK_FUSED_DERIV, DD, CC, FF, GROUP>(p, nblocks, s, ga);
+            return launch_k<R, L, C, NT, MODE, FK_FUSED, DD, CC, FF, GROUP>(p, nblocks, s, ga);
+        };
+        using I2 = std::integral_constant<int, 2>;
+        using I3 = std::integral_constant<int, 3>;
+        using I0 = std::integral_constant<int, 0>;
+        using T_ = std::true_type;
+        using F_ = std::false_type;
+        if (p.fs_L1) {
+            // four-step step B (2D only)
+            if (p.d != 2 || p.post_tw != 2) return hipErrorInvalidValue;
+            return p.table_complex ? by_kind(I2{}, T_{}, I2{}) : by_kind(I2{}, F_{}, I2{});
+        }
+        if (p.d == 3) return p.table_complex ? by_kind(I3{}, T_{}, I0{}) : by_kind(I3{}, F_{}, I0{});
+        return p.table_complex ? by_kind(I2{}, T_{}, I0{}) : by_kind(I2{}, F_{}, I0{});
     }
     if (p.post_tw || p.fs_L1) {
         // four-step step A (column forward with post twiddle)

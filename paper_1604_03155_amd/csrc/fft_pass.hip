@@ -244,6 +244,15 @@ __global__ void __launch_bounds__(256) fft_pass_kernel(PassDesc p) {
         __syncthreads();
         run_fft<R, MODE, +1>(p, t, SRC_LDS, nullptr, b2, b0, DST_GLOBAL, gout, nullptr, false, nullptr);
         run_fft<R, MODE, +1>(p, t, SRC_LDS, nullptr, b1, b0, DST_GLOBAL, gout2, nullptr, false, nullptr);
+    } else if (KIND == KIND_FUSED_DERIV) {
+        // forward -> Khat -> b2; i*kappa spectrum in b1; inverse of b1 only
+        run_fft<R, MODE, -1>(p, t, SRC_GLOBAL, gin, b0, b1, DST_TABLE, nullptr, b2, false, nullptr);
+        for (int i = threadIdx.x; i < CL; i += blockDim.x) {
+            const int e = MODE == MODE_COL ? i / p.C : i % p.L;
+            b1[i] = times_ikappa(b2[i], axis_index(p, e, t.o), axis_len(p), p.kscale);
+        }
+        __syncthreads();
+        run_fft<R, MODE, +1>(p, t, SRC_LDS, nullptr, b1, b0, DST_GLOBAL, gout, nullptr, false, nullptr);
     } else if (KIND == KIND_INV_GRAD) {
         // plain inverse to out; the loads also stash i*kappa*input in b2,
         // whose inverse goes to out2
@@ -264,7 +273,7 @@ __global__ void __launch_bounds__(256) fft_inv_deriv_kernel(PassDesc p) {
 }
 
 int lds_buffers(int kind) {
-    return (kind == KIND_FUSED || kind == KIND_FUSED_GRAD || kind == KIND_INV_GRAD) ? 3 : 2;
+    return (kind == KIND_FUSED || kind == KIND_FUSED_GRAD || kind == KIND_FUSED_DERIV || kind == KIND_INV_GRAD) ? 3 : 2;
 }
 
 template <typename R, int MODE>
@@ -293,6 +302,7 @@ hipError_t launch_typed(const PassDesc& p, int kind, bool deriv_only, hipStream_
             case KIND_INV: fn = fft_pass_kernel<R, MODE, KIND_INV>; break;
             case KIND_FUSED: fn = fft_pass_kernel<R, MODE, KIND_FUSED>; break;
             case KIND_FUSED_GRAD: fn = fft_pass_kernel<R, MODE, KIND_FUSED_GRAD>; break;
+            case KIND_FUSED_DERIV: fn = fft_pass_kernel<R, MODE, KIND_FUSED_DERIV>; break;
             case KIND_INV_GRAD: fn = fft_pass_kernel<R, MODE, KIND_INV_GRAD>; break;
             default: return hipErrorInvalidValue;
         }

@@ -125,7 +125,8 @@ void fill_greens_params(const vg_plan* p, GreensParams& g) {
     g.L = p->L;
     g.ds = 2.0 * M_PI / p->P;
     const double L = p->L, k = p->k;
-    if (p->kernel == VG_HELMHOLTZ && p->d == 3) {
+    const bool helm = p->kernel == VG_HELMHOLTZ || p->kernel == VG_LAPLACE_HELMHOLTZ;
+    if (helm && p->d == 3) {
         // power series of (1/s) int_0^L sin(sr) e^{ikr} dr in x^2 = (sL)^2:
         // a_j = L^2 (-1)^j/(2j+1)! sum_p (ikL)^p / (p! (2j+2+p))
         g.ntaylor = 10;
@@ -140,7 +141,7 @@ void fill_greens_params(const vg_plan* p, GreensParams& g) {
             g.taylor_i[j] = a.imag();
         }
     }
-    if (p->kernel == VG_HELMHOLTZ && p->d == 2) {
+    if (helm && p->d == 2) {
         const double x = k * L;
         const std::complex<double> H0(std::cyl_bessel_j(0.0, x), std::cyl_neumann(0.0, x));
         const std::complex<double> H1(std::cyl_bessel_j(1.0, x), std::cyl_neumann(1.0, x));
@@ -249,7 +250,7 @@ vg_status precompute(vg_plan* p, hipStream_t s, bool keep_T) {
     }
     long long nK = 1;
     for (int i = 0; i < d; ++i) nK *= N1;
-    p->table_complex = (p->kernel == VG_HELMHOLTZ) ? 1 : 0;
+    p->table_complex = (p->kernel == VG_HELMHOLTZ || p->kernel == VG_LAPLACE_HELMHOLTZ) ? 1 : 0;
     const size_t esz = (p->fp64 ? 8 : 4) * (p->table_complex ? 2 : 1);
     p->table_bytes = (size_t)nK * esz;
     if ((he = dev_malloc(&p->table, p->table_bytes)) != hipSuccess) return chk(he, "kernel table");
@@ -304,7 +305,7 @@ int fft_max_lds_bytes_for_device();
 namespace {
 
 int lds_buffers_generic(int kind) {
-    return (kind == KIND_FUSED || kind == KIND_FUSED_GRAD || kind == KIND_INV_GRAD) ? 3 : 2;
+    return (kind == KIND_FUSED || kind == KIND_FUSED_GRAD || kind == KIND_FUSED_DERIV || kind == KIND_INV_GRAD) ? 3 : 2;
 }
 
 // Tile width of one step: the specialised kernel's when one exists for its
@@ -318,7 +319,8 @@ int choose_C(const vg_plan* p, const PassStep& st, bool* specialised) {
     // step A (forward + twiddle), step B (fused, full length) and A' (inverse)
     const bool four = d.post_tw != 0 || d.fs_L1 != 0;
     const bool four_ok = !four || (st.mode == MODE_COL && ((st.kind == KIND_FWD && d.post_tw == 1 && !d.fs_L1) ||
-                                                          ((st.kind == KIND_FUSED || st.kind == KIND_FUSED_GRAD) &&
+                                                          ((st.kind == KIND_FUSED || st.kind == KIND_FUSED_GRAD ||
+                                                            st.kind == KIND_FUSED_DERIV) &&
                                                            d.fs_L1 && d.post_tw == 2 && p->d == 2)));
     if (four_ok && !p->cfg.generic && !std::getenv("VG_GENERIC_PASSES")) {
         const int fc = fast_pass_C(d.L, st.mode, p->fp64);
@@ -446,6 +448,16 @@ vg_status build_programs(vg_plan* p, hipStream_t stream) {
     const int W0 = BUF_WS0, W1 = BUF_WS0 + 1, W2 = BUF_WS0 + 2, W3 = BUF_WS0 + 3, W4 = BUF_WS0 + 4;
     Program& A = p->apply_prog;
     Program& G = p->grad_prog;
+    // Long specialised columns (2N >= 512) run the fused gradient pass as two
+    // passes (derivative spectrum, then phi's) that each keep the register
+    // budget of a plain fused pass: the single two-output pass holds two
+    // spectra per thread and drops to 1 wave per SIMD (measured at N = 256:
+    // 0.93 -> 0.36 + 0.33 ms; at N = 128 the single pass is faster, 0.065 vs
+    // 0.096 ms).  Shorter or generic columns keep the single pass.
+    auto split_fused_grad = [&](long long len) {
+        return !p->cfg.generic && len >= 512 && fast_pass_C((int)len, MODE_COL, p->fp64) > 0;
+    };
+    const bool split_grad = split_fused_grad(L);
     A.steps.clear();
     G.steps.clear();
     if (p->d == 3) {
@@ -465,8 +477,15 @@ vg_status build_programs(vg_plan* p, hipStream_t stream) {
         set_ws(G, {b2, b4, b4, b2, b2});
         G.steps.push_back(row_step(p, KIND_FWD, BUF_F, N, (int)N, W0, L, (int)L, N * N, "g1_row_fwd"));
         G.steps.push_back(col_step(p, KIND_FWD, W0, PS, L, (int)N, W1, PL, L, (int)L, L, N, "g2_col_fwd"));
-        G.steps.push_back(col_step(p, KIND_FUSED_GRAD, W1, 0, PL, (int)N, W1, 0, PL, (int)N, L * L, 1,
-                                   "g3_fused_grad", W2));
+        if (split_grad) {
+            // derivative spectrum first (W1 -> W2), then phi's in place
+            G.steps.push_back(col_step(p, KIND_FUSED_DERIV, W1, 0, PL, (int)N, W2, 0, PL, (int)N, L * L, 1,
+                                       "g3_fused_deriv"));
+            G.steps.push_back(col_step(p, KIND_FUSED, W1, 0, PL, (int)N, W1, 0, PL, (int)N, L * L, 1, "g3_fused"));
+        } else {
+            G.steps.push_back(col_step(p, KIND_FUSED_GRAD, W1, 0, PL, (int)N, W1, 0, PL, (int)N, L * L, 1,
+                                       "g3_fused_grad", W2));
+        }
         G.steps.push_back(col_step(p, KIND_INV_GRAD, W1, PL, L, (int)L, W0, PS, L, (int)N, L, N,
                                    "g4_col_inv_grad", W3));
         G.steps.push_back(col_step(p, KIND_INV, W2, PL, L, (int)L, W4, PS, L, (int)N, L, N, "g4_col_inv"));
@@ -487,8 +506,14 @@ vg_status build_programs(vg_plan* p, hipStream_t stream) {
             A.steps.push_back(row_step(p, KIND_INV, W0, RP, (int)L, BUF_PHI, N, (int)N, N, "p3_row_inv"));
             set_ws(G, {b2, b2});
             G.steps.push_back(row_step(p, KIND_FWD, BUF_F, N, (int)N, W0, RP, (int)L, N, "g1_row_fwd"));
-            G.steps.push_back(col_step(p, KIND_FUSED_GRAD, W0, 0, RP, (int)N, W0, 0, RP, (int)N, L, 1,
-                                       "g2_fused_grad", W1));
+            if (split_grad) {
+                G.steps.push_back(col_step(p, KIND_FUSED_DERIV, W0, 0, RP, (int)N, W1, 0, RP, (int)N, L, 1,
+                                           "g2_fused_deriv"));
+                G.steps.push_back(col_step(p, KIND_FUSED, W0, 0, RP, (int)N, W0, 0, RP, (int)N, L, 1, "g2_fused"));
+            } else {
+                G.steps.push_back(col_step(p, KIND_FUSED_GRAD, W0, 0, RP, (int)N, W0, 0, RP, (int)N, L, 1,
+                                           "g2_fused_grad", W1));
+            }
             G.steps.push_back(row_step(p, KIND_INV_GRAD, W0, RP, (int)L, BUF_PHI, N, (int)N, N, "g3_row_inv_grad",
                                        BUF_GRAD0 + 1));
             G.steps.push_back(row_step(p, KIND_INV, W1, RP, (int)L, BUF_GRAD0 + 0, N, (int)N, N, "g3_row_inv_d1"));
@@ -507,10 +532,10 @@ vg_status build_programs(vg_plan* p, hipStream_t stream) {
                 s.desc.post_tw = kind == KIND_FWD ? 1 : 0;
                 return s;
             };
-            auto stepB = [&](int kind, int buf, int buf2, const char* name) {
+            auto stepB = [&](int kind, int buf, int buf2, const char* name, int obuf = -1) {
                 // outer k1 (offset L2 rows), columns, elements n2 (stride one row)
-                PassStep s = col_step(p, kind, buf, (long long)L2 * RP, RP, L2, buf, (long long)L2 * RP, RP, L2, L, L1,
-                                      name, buf2, L2);
+                PassStep s = col_step(p, kind, buf, (long long)L2 * RP, RP, L2, obuf < 0 ? buf : obuf, (long long)L2 * RP,
+                                      RP, L2, L, L1, name, buf2, L2);
                 s.desc.L_big = (int)L;
                 s.desc.post_tw = 2;
                 s.desc.fs_L1 = L1;
@@ -525,7 +550,12 @@ vg_status build_programs(vg_plan* p, hipStream_t stream) {
             set_ws(G, {bL, bL});
             G.steps.push_back(row_step(p, KIND_FWD, BUF_F, N, (int)N, W0, RP, (int)L, N, "g1_row_fwd"));
             G.steps.push_back(stepA(KIND_FWD, W0, "g2a_col_fwd"));
-            G.steps.push_back(stepB(KIND_FUSED_GRAD, W0, W1, "g2b_fused_grad"));
+            if (split_fused_grad(L2)) {
+                G.steps.push_back(stepB(KIND_FUSED_DERIV, W0, BUF_NONE, "g2b_fused_deriv", W1));
+                G.steps.push_back(stepB(KIND_FUSED, W0, BUF_NONE, "g2b_fused"));
+            } else {
+                G.steps.push_back(stepB(KIND_FUSED_GRAD, W0, W1, "g2b_fused_grad"));
+            }
             G.steps.push_back(stepA(KIND_INV, W0, "g2c_col_inv"));
             G.steps.push_back(stepA(KIND_INV, W1, "g2c_col_inv_d1"));
             G.steps.push_back(row_step(p, KIND_INV_GRAD, W0, RP, (int)L, BUF_PHI, N, (int)N, N, "g3_row_inv_grad",
@@ -564,7 +594,7 @@ double pass_bytes(const vg_plan* p, const PassStep& s) {
     const double pencils = (s.mode == MODE_COL) ? (double)s.desc.outer * s.desc.inner : (double)s.desc.outer;
     double outs = (s.out2_buf != BUF_NONE) ? 2.0 : 1.0;
     double b = pencils * es * (s.desc.n_in + outs * s.desc.n_out);
-    if (s.kind == KIND_FUSED || s.kind == KIND_FUSED_GRAD) b += (double)p->table_bytes;
+    if (s.kind == KIND_FUSED || s.kind == KIND_FUSED_GRAD || s.kind == KIND_FUSED_DERIV) b += (double)p->table_bytes;
     return b;
 }
 }  // namespace

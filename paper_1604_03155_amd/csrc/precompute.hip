@@ -1,7 +1,8 @@
 // FP64 plan precompute (Sections 2 and 4).
 //
 // 1. Kernel spectrum: G^L(|s_m|) on the P N-per-axis lattice s_m = (2 pi/P) m
-//    (Section 2), from the closed forms of Table 1 (3D) and Table 2 (2D).
+//    (Section 2), from the closed forms of Table 1 (3D) and Table 2 (2D):
+//    Laplace, Helmholtz, biharmonic and Delta (Delta + k^2).
 //    Where a printed form is 0/0 (s = 0, s = k) an algebraically equal form or
 //    a series of the same radial integral is used.
 // 2. T(n) = M^-d sum_m G(|s_m|) e^{2 pi i m.n/M}, n in [0, N)^d.  G depends on
@@ -125,9 +126,65 @@ __device__ c64 g_helmholtz2d(double s, const GreensParams& g) {
     return mk(nr / den, ni / den);
 }
 
+// Table 1, Delta^2 (kernel r/(8 pi)):
+//   G = [(2 - x^2) cos x + 2 x sin x - 2] / (2 s^4),  x = L s;
+// for x < 1 (where the numerator cancels to O(x^4)) the power series of the
+// radial integral (1/(2s)) int_0^L r^2 sin(sr) dr:
+//   G = (L^4/2) sum_n (-1)^n x^(2n) / ((2n + 4)(2n + 1)!).
+__device__ c64 g_biharmonic3d(double s, const GreensParams& g) {
+    const double L = g.L, x = L * s;
+    if (x < 1.0) {
+        const double x2 = x * x;
+        double term = 1.0, acc = 0.0;  // term = (-1)^n x^(2n) / (2n+1)!
+        for (int n = 0; n < 12; ++n) {
+            acc += term / (2 * n + 4);
+            term *= -x2 / ((2.0 * n + 2.0) * (2.0 * n + 3.0));
+        }
+        return mk(0.5 * L * L * L * L * acc, 0.0);
+    }
+    double sn, cs;
+    sincos(x, &sn, &cs);
+    const double s2 = s * s;
+    return mk(((2.0 - x * x) * cs + 2.0 * x * sn - 2.0) / (2.0 * s2 * s2), 0.0);
+}
+
+// Table 2, Delta^2 (kernel -(r^2/(8 pi))(log r - 1)):
+//   G = (J0(x) - 1)/s^4 - L^3 (log L - 1) J1(x)/(4s) + L log L J1(x)/s^3
+//       - L^2 (2 log L - 1) J0(x)/(4 s^2),  x = L s;
+// for x < 1 the series of -(1/4) int_0^L r^3 (log r - 1) J0(sr) dr:
+//   G = -(L^4/4) sum_n (-1)^n (x/2)^(2n)/(n!)^2 [(log L - 1)/(2n+4) - 1/(2n+4)^2].
+__device__ c64 g_biharmonic2d(double s, const GreensParams& g) {
+    const double L = g.L, x = L * s, lg = log(L);
+    if (x < 1.0) {
+        const double q = 0.25 * x * x;
+        double term = 1.0, acc = 0.0;  // term = (-1)^n (x/2)^(2n) / (n!)^2
+        for (int n = 0; n < 14; ++n) {
+            const double m1 = 2.0 * n + 4.0;
+            acc += term * ((lg - 1.0) / m1 - 1.0 / (m1 * m1));
+            term *= -q / ((n + 1.0) * (n + 1.0));
+        }
+        return mk(-0.25 * L * L * L * L * acc, 0.0);
+    }
+    const double J0 = j0(x), J1 = j1(x), s2 = s * s;
+    return mk((J0 - 1.0) / (s2 * s2) - L * L * L * (lg - 1.0) * J1 / (4.0 * s) + L * lg * J1 / (s2 * s) -
+                  L * L * (2.0 * lg - 1.0) * J0 / (4.0 * s2),
+              0.0);
+}
+
+// kernel: 0 Delta, 1 Delta + k^2, 2 Delta^2, 3 Delta (Delta + k^2) (G_k - G_0)
 __device__ __forceinline__ c64 g_eval(double s, const GreensParams& g) {
-    if (g.d == 3) return g.kernel == 0 ? g_laplace3d(s, g) : g_helmholtz3d(s, g);
-    return g.kernel == 0 ? g_laplace2d(s, g) : g_helmholtz2d(s, g);
+    if (g.d == 3) {
+        if (g.kernel == 0) return g_laplace3d(s, g);
+        if (g.kernel == 1) return g_helmholtz3d(s, g);
+        if (g.kernel == 2) return g_biharmonic3d(s, g);
+        const c64 a = g_helmholtz3d(s, g), b = g_laplace3d(s, g);
+        return mk(a.x - b.x, a.y - b.y);
+    }
+    if (g.kernel == 0) return g_laplace2d(s, g);
+    if (g.kernel == 1) return g_helmholtz2d(s, g);
+    if (g.kernel == 2) return g_biharmonic2d(s, g);
+    const c64 a = g_helmholtz2d(s, g), b = g_laplace2d(s, g);
+    return mk(a.x - b.x, a.y - b.y);
 }
 
 // Y[row, n] = sum_m Cm[n][m] X[row, m], X complex, Cm real (Nout x K).

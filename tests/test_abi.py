@@ -46,6 +46,9 @@ BAD = [
     (dict(d=3, N=8, kernel=1, k=0.0), 1),     # Helmholtz needs k > 0
     (dict(d=3, N=8, kernel=1, k=float("nan")), 1),
     (dict(d=3, N=8, kernel=7), 1),       # unknown kernel
+    (dict(d=3, N=8, kernel=4), 1),
+    (dict(d=2, N=8, kernel=3, k=0.0), 1),     # Delta(Delta + k^2) needs k > 0
+    (dict(d=2, N=8, kernel=3, k=-2.0), 1),
     (dict(d=3, N=8, L=1.5), 1),          # L below sqrt(3)
     (dict(d=2, N=8, L=1.2), 1),          # L below sqrt(2)
     (dict(d=3, N=8, P=2), 1),            # P not above 1 + L

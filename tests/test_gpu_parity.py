@@ -57,6 +57,8 @@ TABLE_CASES = [
     (3, 4, "laplace", 0.0), (3, 8, "laplace", 0.0), (3, 8, "helmholtz", 20.0), (3, 12, "helmholtz", 0.4),
     (3, 10, "helmholtz", 7.5), (2, 16, "laplace", 0.0), (2, 16, "helmholtz", 30.0), (2, 20, "helmholtz", 2.0),
     (2, 30, "helmholtz", 200.0), (2, 6, "laplace", 0.0),
+    (3, 8, "biharmonic", 0.0), (3, 10, "laplace_helmholtz", 6.0), (2, 16, "biharmonic", 0.0),
+    (2, 20, "laplace_helmholtz", 15.0), (2, 40, "biharmonic", 0.0),
 ]
 
 
@@ -90,6 +92,8 @@ APPLY_CASES = [
     (2, 4, "laplace", 0.0), (2, 6, "helmholtz", 3.0), (2, 10, "laplace", 0.0), (2, 14, "helmholtz", 40.0),
     (2, 30, "laplace", 0.0), (2, 64, "helmholtz", 60.0), (2, 100, "laplace", 0.0), (2, 256, "helmholtz", 100.0),
     (2, 48, "helmholtz", 21.0), (2, 96, "laplace", 0.0), (2, 128, "helmholtz", 75.0), (2, 512, "laplace", 0.0),
+    (3, 16, "biharmonic", 0.0), (3, 32, "laplace_helmholtz", 10.0), (3, 48, "biharmonic", 0.0),
+    (2, 30, "laplace_helmholtz", 20.0), (2, 64, "biharmonic", 0.0), (2, 256, "laplace_helmholtz", 50.0),
 ]
 
 
@@ -113,7 +117,9 @@ def test_apply_matches_oracle(d, N, kernel, k, precision):
                                           (3, 20, "helmholtz", 13.0), (2, 16, "helmholtz", 25.0),
                                           (2, 30, "laplace", 0.0), (2, 64, "helmholtz", 7.0),
                                           (3, 32, "helmholtz", 10.0), (3, 48, "laplace", 0.0),
-                                          (2, 96, "helmholtz", 40.0), (2, 256, "laplace", 0.0)])
+                                          (2, 96, "helmholtz", 40.0), (2, 256, "laplace", 0.0),
+                                          (3, 32, "biharmonic", 0.0), (2, 64, "laplace_helmholtz", 12.0),
+                                          (2, 256, "biharmonic", 0.0)])
 def test_gradient_matches_oracle(d, N, kernel, k, precision):
     say("gradient", d, N, kernel, k, precision)
     vg = _vg()
@@ -268,3 +274,35 @@ def test_2d_n4096_workload_against_closed_form(name):
     err = np.linalg.norm(g - ref) / np.linalg.norm(ref)
     say(name, "targets", ntarget, "rel L2", err)
     assert err <= FP32_TOL
+
+
+@pytest.mark.parametrize("d,N,kernel,k", [(3, 64, "biharmonic", 0.0), (3, 64, "laplace_helmholtz", 12.0),
+                                          (2, 256, "biharmonic", 0.0)])
+def test_other_kernels_against_gaussian_closed_forms(d, N, kernel, k):
+    """The biharmonic and Delta(Delta + k^2) kernels end to end: a seeded sum of
+    resolved, contained Gaussians (pi sigma N >= 10, >= 7 sigma from the
+    boundary) against the Section 5.1 closed forms (with the readings of the
+    oracle) for the potential and the gradient, FP32 and FP64."""
+    say("closed form", d, N, kernel, k)
+    from oracle import closed_form as cf
+    from workloads import draw_gaussian_sum, evaluate_grid, grid_coords
+    vg = _vg()
+    torch = _torch()
+    sig = (0.05, 0.06) if d == 3 else (0.02, 0.03)
+    src = draw_gaussian_sum(500 + N, d, 3, 0.1, sig)
+    f = evaluate_grid(src, N)
+    x = grid_coords(N)
+    rng = np.random.default_rng(13)
+    idx = rng.integers(0, N, size=(400, d))
+    pts = np.stack([x[idx[:, a]] for a in range(d)], axis=1)
+    u = cf.gaussian_sum_potential(d, kernel, k, src.centers, src.sigmas, src.amps, pts)
+    du = cf.gaussian_sum_gradient(d, kernel, k, src.centers, src.sigmas, src.amps, pts)
+    for precision, tol in (("fp32", FP32_TOL), ("fp64", 1e-10)):
+        p = vg.Plan(d, N, kernel, k, precision=precision)
+        phi, grad = p.gradient(to_dev(f, precision))
+        torch.cuda.synchronize()
+        ph = phi.cpu().numpy()[tuple(idx.T)]
+        gr = np.stack([grad[j].cpu().numpy()[tuple(idx.T)] for j in range(d)])
+        ep, eg = rel_l2(ph, u), rel_l2(gr, du)
+        say("  ", precision, "phi", ep, "grad", eg)
+        assert ep <= tol and eg <= tol
