@@ -192,6 +192,40 @@ vg_status vg_apply_batched(int count, const vg_plan* const* plans,
                            void* workspace, void* stream);
 
 /*
+ * Lippmann-Schwinger solve (Section 5.3, the dual form of the equation): find
+ * the density sigma of the scattered field phi_s = g_k * sigma from
+ *     -sigma + k^2 q (g_k * sigma) = -k^2 q phi_in
+ * by Bi-CGStab (Section 5.3's iteration) started from sigma = 0, with the
+ * plan's convolution as the matrix-vector product (two per iteration).
+ * plan: a VG_HELMHOLTZ plan (k is the plan's wavenumber).
+ * q, phi_in: device arrays of N^d complex (the plan's precision), the
+ *   contrast (compactly supported inside the box) and the incident field on
+ *   the grid; sigma: device array of N^d complex, the solution.
+ * tol: stop when the residual 2-norm is at most tol times that of the
+ *   right-hand side; max_iter >= 1 iterations at most.
+ * workspace: vg_ls_workspace_size(plan) bytes, or NULL (allocated and freed
+ *   inside the call).
+ * Synchronous: the call waits on `stream` once per dot product and returns
+ * when the iteration stops.  result (may be NULL): iterations, matrix-vector
+ * products, final relative residual (of the recurrence), converged flag; not
+ * converging within max_iter (or a Bi-CGStab breakdown) is reported there,
+ * with status VG_OK.
+ * Errors: VG_ERR_INVALID_ARG (NULL arrays, not a Helmholtz plan, tol <= 0,
+ * max_iter < 1), VG_ERR_OUT_OF_MEMORY, VG_ERR_DEVICE.
+ */
+typedef struct vg_ls_result {
+    int iterations;
+    int matvecs;
+    double residual;
+    int converged;
+} vg_ls_result;
+
+size_t vg_ls_workspace_size(const vg_plan* plan);
+vg_status vg_ls_solve(const vg_plan* plan, const void* q, const void* phi_in, void* sigma,
+                      double tol, int max_iter, void* workspace, void* stream,
+                      vg_ls_result* result);
+
+/*
  * Copy plan tables to host memory, converted to complex128 (interleaved
  * doubles).  Synchronous.
  *   vg_plan_kernel_hat: Khat(m) on the octant m in [0, N]^d, (N+1)^d values,

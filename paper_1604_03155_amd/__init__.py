@@ -4,7 +4,7 @@ Thin ctypes marshalling over the C ABI declared in include/vg.h: every step of
 the computation (kernel precompute, FFT passes, multiplies) runs in the HIP
 library.  PyTorch provides device memory and streams only.  There is no
 fallback: importing this package fails if the library has not been built
-(`python -m paper_1604_03155_amd.build`).
+(`python paper_1604_03155_amd/build.py`).
 
 Method: Vico, Greengard, Ferrando, "Fast convolution with free-space Green's
 functions" -- the truncated-kernel FFT convolution phi = g * f on the uniform
@@ -29,7 +29,7 @@ _TUNE = {"off": 0, "quick": 1, "full": 2}
 _KERNELS = {"laplace": LAPLACE, "helmholtz": HELMHOLTZ, "biharmonic": BIHARMONIC, "laplace_helmholtz": LAPLACE_HELMHOLTZ}
 
 if not os.path.exists(LIBRARY_PATH):
-    raise ImportError(f"{LIBRARY_PATH} is missing: build it with `python -m paper_1604_03155_amd.build`")
+    raise ImportError(f"{LIBRARY_PATH} is missing: build it with `python paper_1604_03155_amd/build.py`")
 
 _lib = ctypes.CDLL(LIBRARY_PATH)
 
@@ -47,6 +47,11 @@ class _Info(ctypes.Structure):
                 ("tune", ctypes.c_int), ("tune_ms", ctypes.c_double), ("tune_candidates", ctypes.c_int),
                 ("pad_bytes", ctypes.c_int), ("xcd_map", ctypes.c_int), ("four_step_L1", ctypes.c_int),
                 ("generic_passes", ctypes.c_int)]
+
+
+class _LsResult(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("matvecs", ctypes.c_int), ("residual", ctypes.c_double),
+                ("converged", ctypes.c_int)]
 
 
 class _PassTime(ctypes.Structure):
@@ -73,6 +78,9 @@ _sig = {
     "vg_profiler_enable": (ctypes.c_int, [ctypes.c_int]),
     "vg_profiler_collect": (ctypes.c_int, [ctypes.POINTER(_PassTime), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "vg_hbm_copy": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp]),
+    "vg_ls_workspace_size": (ctypes.c_size_t, [_vp]),
+    "vg_ls_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _vp, _vp,
+                                   ctypes.POINTER(_LsResult)]),
     "vg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "vg_last_error": (ctypes.c_char_p, []),
 }
@@ -201,6 +209,25 @@ class Plan:
         _check(_lib.vg_gradient(self._h, _vp(f.data_ptr()), _vp(phi.data_ptr()) if phi is not None else None,
                                 _vp(grad.data_ptr()), ws, _stream_ptr(stream)), "vg_gradient")
         return phi, grad
+
+    def ls_solve(self, q, phi_in, tol=1e-12, max_iter=500, sigma=None, workspace=None, stream=None):
+        """Density sigma of the scattered field of the Lippmann-Schwinger
+        equation -sigma + k^2 q (g_k * sigma) = -k^2 q phi_in (Section 5.3),
+        by Bi-CGStab on the device.  Returns (sigma, info dict)."""
+        torch = _torch()
+        self._check_array(q, "q")
+        self._check_array(phi_in, "phi_in")
+        if sigma is None:
+            sigma = torch.empty_like(phi_in)
+        self._check_array(sigma, "sigma")
+        res = _LsResult()
+        ws = _vp(workspace.data_ptr()) if workspace is not None else None
+        _check(_lib.vg_ls_solve(self._h, _vp(q.data_ptr()), _vp(phi_in.data_ptr()), _vp(sigma.data_ptr()),
+                                float(tol), int(max_iter), ws, _stream_ptr(stream), ctypes.byref(res)), "vg_ls_solve")
+        return sigma, {f: getattr(res, f) for f, _ in _LsResult._fields_}
+
+    def ls_workspace_size(self):
+        return int(_lib.vg_ls_workspace_size(self._h))
 
     def kernel_hat(self):
         """Khat on the octant [0, N]^d as complex128 numpy (Section 4)."""

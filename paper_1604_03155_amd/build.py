@@ -1,6 +1,6 @@
 """Build the HIP library libvgconv.so for gfx950, in-tree.
 
-    python -m paper_1604_03155_amd.build [--jobs N]
+    python paper_1604_03155_amd/build.py [--jobs N]
 
 Every source under csrc/ is compiled with hipcc (as HIP, so host-only files
 may include the HIP runtime) and linked into paper_1604_03155_amd/libvgconv.so.

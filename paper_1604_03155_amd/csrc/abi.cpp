@@ -15,6 +15,9 @@ vg_status batched_apply(int count, const vg_plan* const* plans, const void* cons
                         void* workspace, hipStream_t stream);
 size_t batched_workspace_size(int count, const vg_plan* const* plans);
 void batched_release_plan(const vg_plan* p);
+size_t ls_workspace_size(const vg_plan* p);
+vg_status ls_solve(const vg_plan* p, const void* q, const void* phi_in, void* sigma, double tol, int max_iter,
+                   void* workspace, hipStream_t st, vg_ls_result* res);
 int fft_max_lds_bytes_for_device();
 }  // namespace vg
 
@@ -201,6 +204,21 @@ vg_status vg_apply_batched(int count, const vg_plan* const* plans, const void* c
                 return fail(VG_ERR_INVALID_ARG, "all plans of a batch must share one precision");
         }
         return batched_apply(count, plans, f, phi, workspace, reinterpret_cast<hipStream_t>(stream));
+    });
+}
+
+size_t vg_ls_workspace_size(const vg_plan* p) { return p ? ls_workspace_size(p) : 0; }
+
+vg_status vg_ls_solve(const vg_plan* p, const void* q, const void* phi_in, void* sigma, double tol, int max_iter,
+                      void* workspace, void* stream, vg_ls_result* result) {
+    return guarded([&]() -> vg_status {
+        if (!p || !q || !phi_in || !sigma) return fail(VG_ERR_INVALID_ARG, "NULL argument");
+        if (p->kernel != VG_HELMHOLTZ) return fail(VG_ERR_INVALID_ARG, "the Lippmann-Schwinger solve needs a Helmholtz plan");
+        if (!(tol > 0.0) || max_iter < 1) return fail(VG_ERR_INVALID_ARG, "tol must be positive and max_iter >= 1");
+        vg_ls_result local;
+        vg_status st = ls_solve(p, q, phi_in, sigma, tol, max_iter, workspace, reinterpret_cast<hipStream_t>(stream),
+                                result ? result : &local);
+        return st;
     });
 }
 

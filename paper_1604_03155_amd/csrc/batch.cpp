@@ -73,11 +73,13 @@ bool env_flag(const char* name) {
     return v && *v && std::strcmp(v, "0") != 0;
 }
 
-// Group key of a specialised pass: everything that selects the kernel.
+// Group key of a specialised pass: everything that selects the kernel (the
+// table's dimension and type only matter to the fused kinds).
 using GroupKey = std::tuple<int, int, int, int, int, int, int, int, int>;
 GroupKey key_of(const BoundStep& b) {
-    return GroupKey(b.desc.L, b.mode, b.kind, b.desc.C, b.desc.d, b.desc.table_complex, b.desc.post_tw,
-                    b.desc.fs_L1 != 0 ? 1 : 0, b.desc.specialised);
+    const bool fused = b.kind == KIND_FUSED || b.kind == KIND_FUSED_GRAD || b.kind == KIND_FUSED_DERIV;
+    return GroupKey(b.desc.L, b.mode, b.kind, b.desc.C, fused ? b.desc.d : 0, fused ? b.desc.table_complex : 0,
+                    b.desc.post_tw, b.desc.fs_L1 != 0 ? 1 : 0, b.desc.specialised);
 }
 
 vg_status build_entry(BatchEntry& e) {
