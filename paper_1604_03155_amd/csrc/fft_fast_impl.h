@@ -122,6 +122,13 @@ __device__ __forceinline__ void st_off(void* base, unsigned off, T v) {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
 }
 
+// A value known to be the same in every lane, passed through readfirstlane:
+// the compiler keeps it in a scalar register and cannot factor it into
+// per-element vector multiplies.
+__device__ __forceinline__ unsigned uniform_u32(unsigned v) { return __builtin_amdgcn_readfirstlane(v); }
+
+
+
 template <int DIR, typename R>
 __device__ __forceinline__ cplx<R> twmul(cplx<R> v, cplx<R> w) {
     return DIR < 0 ? cmul(v, w) : cmulc(v, w);
@@ -375,7 +382,10 @@ __device__ __forceinline__ void table_fetch(cplx<R>* kt, const void* __restrict_
     constexpr int RAD = P.r[P.n - 1];
     constexpr int E = C * L / NT;
     const int N1 = tabN + 1;
-    const unsigned plane = (D == 3) ? (unsigned)(N1 * N1) : (unsigned)N1;
+    // block strides as opaque scalars: per element one add, no multiply
+    const unsigned plane = uniform_u32((D == 3) ? (unsigned)(N1 * N1) : (unsigned)N1);
+    constexpr int LR = L / RAD;
+    const unsigned step = uniform_u32((unsigned)LR * plane);
 #pragma unroll
     for (int i = 0; i < E / RAD; ++i) {
         int q, j;
@@ -389,15 +399,15 @@ __device__ __forceinline__ void table_fetch(cplx<R>* kt, const void* __restrict_
             rowoff = (unsigned)min(col, L - col);
         }
         const unsigned jp = (unsigned)j * plane;
+        const unsigned lo = rowoff + jp, hi = rowoff - jp;  // hi wraps; every flat index below is in range
 #pragma unroll
         for (int r = 0; r < RAD; ++r) {
             // e = j + r L/R with 0 <= j < L/R: the octant fold min(e, L - e) is
             // e on blocks below L/2 and L - e on blocks at or above it.
-            constexpr int LR = L / RAD;
             const int e = j + r * LR;
             unsigned flat;
-            if ((r + 1) * LR <= L / 2) flat = (unsigned)(r * LR) * plane + jp + rowoff;
-            else if (r * LR >= L / 2) flat = (unsigned)(L - r * LR) * plane - jp + rowoff;
+            if ((r + 1) * LR <= L / 2) flat = lo + (unsigned)r * step;
+            else if (r * LR >= L / 2) flat = hi + (unsigned)(RAD - r) * step;
             else flat = (unsigned)min(e, L - e) * plane + rowoff;
             if constexpr (CPLX) {
                 kt[i * RAD + r] = ld_off<cplx<R>>(table, flat * (unsigned)sizeof(cplx<R>));
