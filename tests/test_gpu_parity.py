@@ -306,3 +306,22 @@ def test_other_kernels_against_gaussian_closed_forms(d, N, kernel, k):
         ep, eg = rel_l2(ph, u), rel_l2(gr, du)
         say("  ", precision, "phi", ep, "grad", eg)
         assert ep <= tol and eg <= tol
+
+
+@pytest.mark.parametrize("d,N,kernel,k,L,P", [(3, 16, "helmholtz", 9.0, 2.0, 5), (2, 32, "laplace", 0.0, 1.6, 3),
+                                              (3, 12, "biharmonic", 0.0, 1.9, 6), (2, 48, "helmholtz", 20.0, 2.5, 4)])
+def test_truncation_radius_and_oversampling_options(d, N, kernel, k, L, P):
+    """Non-default truncation radius L (> sqrt(d)) and oversampling P (> 1 + L),
+    Section 2: tables and apply against the oracle built with the same L, P."""
+    say("options", d, N, kernel, k, L, P)
+    from oracle import operator as op
+    vg = _vg()
+    torch = _torch()
+    p = vg.Plan(d, N, kernel, k, precision="fp64", L=L, P=P, keep_operator=True)
+    o = op.Plan(d, N, kernel, k, L=L, P=P)
+    assert np.max(np.abs(p.operator_entries() - o.T_oct)) <= FP64_TOL * np.max(np.abs(o.T_oct))
+    assert np.max(np.abs(p.kernel_hat() - o.K_oct)) <= FP64_TOL * np.max(np.abs(o.K_oct))
+    f = random_density(600 + N, d, N)
+    phi = p.apply(to_dev(f, "fp64"))
+    torch.cuda.synchronize()
+    assert rel_l2(phi.cpu().numpy(), o.apply(f)) <= FP64_TOL
