@@ -167,6 +167,22 @@ vg_status vg_gradient(const vg_plan* plan, const void* f, void* phi, void* grad,
                       void* workspace, void* stream);
 
 /*
+ * Real densities: phi = T * f for real f and
+ * a real kernel (VG_LAPLACE, VG_BIHARMONIC), where T is real (Sections 2 and
+ * 4) and so is phi.  f, phi: device arrays of N^d float (double for FP64
+ * plans), C order, the grid of vg_apply; f == phi allowed.  The transforms
+ * run on the half spectrum of the last axis (N + 1 of 2N values; a real row
+ * is processed as N/2 complex pairs), moving about half the bytes of
+ * vg_apply.  workspace: vg_real_workspace_size(plan) bytes, or NULL.
+ * Asynchronous on `stream`.
+ * Errors: VG_ERR_INVALID_ARG (NULL arguments, complex kernel),
+ * VG_ERR_UNSUPPORTED_SIZE (no length-specialised kernels for N or 2N),
+ * VG_ERR_DEVICE.
+ */
+size_t vg_real_workspace_size(const vg_plan* plan);
+vg_status vg_apply_real(const vg_plan* plan, const void* f, void* phi, void* workspace, void* stream);
+
+/*
  * Apply `count` plans to `count` densities in one go: phi[i] = T_i * f[i]
  * (Section 4 applied to a set of independent densities).  Plans may mix d, N,
  * kernel and k; all must share one precision and live on the current device.

@@ -79,6 +79,8 @@ _sig = {
     "vg_profiler_collect": (ctypes.c_int, [ctypes.POINTER(_PassTime), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "vg_hbm_copy": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp]),
     "vg_ls_workspace_size": (ctypes.c_size_t, [_vp]),
+    "vg_real_workspace_size": (ctypes.c_size_t, [_vp]),
+    "vg_apply_real": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "vg_ls_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _vp, _vp,
                                    ctypes.POINTER(_LsResult)]),
     "vg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -209,6 +211,28 @@ class Plan:
         _check(_lib.vg_gradient(self._h, _vp(f.data_ptr()), _vp(phi.data_ptr()) if phi is not None else None,
                                 _vp(grad.data_ptr()), ws, _stream_ptr(stream)), "vg_gradient")
         return phi, grad
+
+    def apply_real(self, f, out=None, workspace=None, stream=None):
+        """phi = T * f for a real density f and a real kernel (Laplace,
+        biharmonic): float32 / float64 arrays of shape (N,)*d."""
+        torch = _torch()
+        rdt = torch.float64 if self.precision == "fp64" else torch.float32
+        for a, name in ((f, "f"), (out, "out")):
+            if a is None:
+                continue
+            if not isinstance(a, torch.Tensor) or not a.is_cuda:
+                raise TypeError(f"{name} must be a CUDA tensor")
+            if a.dtype != rdt or tuple(a.shape) != self.shape or not a.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous {rdt} tensor of shape {self.shape}")
+        if out is None:
+            out = torch.empty_like(f)
+        ws = _vp(workspace.data_ptr()) if workspace is not None else None
+        _check(_lib.vg_apply_real(self._h, _vp(f.data_ptr()), _vp(out.data_ptr()), ws, _stream_ptr(stream)),
+               "vg_apply_real")
+        return out
+
+    def real_workspace_size(self):
+        return int(_lib.vg_real_workspace_size(self._h))
 
     def ls_solve(self, q, phi_in, tol=1e-12, max_iter=500, sigma=None, workspace=None, stream=None):
         """Density sigma of the scattered field of the Lippmann-Schwinger

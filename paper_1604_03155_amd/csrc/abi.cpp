@@ -188,6 +188,23 @@ vg_status vg_gradient(const vg_plan* p, const void* f, void* phi, void* grad, vo
     });
 }
 
+size_t vg_real_workspace_size(const vg_plan* p) { return p ? p->real_prog.ws_bytes : 0; }
+
+vg_status vg_apply_real(const vg_plan* p, const void* f, void* phi, void* workspace, void* stream) {
+    return guarded([&]() -> vg_status {
+        if (!p) return fail(VG_ERR_INVALID_ARG, "plan is NULL");
+        if (!f || !phi) return fail(VG_ERR_INVALID_ARG, "f and phi must be device pointers");
+        if (p->table_complex)
+            return fail(VG_ERR_INVALID_ARG, "real applies need a real kernel (VG_LAPLACE or VG_BIHARMONIC)");
+        if (p->real_prog.steps.empty())
+            return fail(VG_ERR_UNSUPPORTED_SIZE, "no real-data kernels for this N (needs specialised lengths N and 2N)");
+        void* ws = nullptr;
+        vg_status st = get_ws(p, p->real_prog.ws_bytes, workspace, &ws);
+        if (st != VG_OK) return st;
+        return run_program(p, p->real_prog, f, phi, nullptr, ws, reinterpret_cast<hipStream_t>(stream));
+    });
+}
+
 size_t vg_batched_workspace_size(int count, const vg_plan* const* plans) {
     if (count <= 0 || !plans) return 0;
     return batched_workspace_size(count, plans);

@@ -98,6 +98,12 @@ struct PassDesc {
     // specialised kernels: 1 maps workgroup slots to tiles XCD by XCD (each
     // of the 8 XCDs gets a contiguous range of tiles), 0 keeps launch order
     int xcd_map;
+    // real-data passes (specialised kernels only): 1 rows of a real array
+    // (read as L complex pairs) -> the L + 1 spectral values of the 2L-point
+    // real transform; 2 the inverse (L + 1 values -> 2L reals, kept half
+    // written as L complex pairs); 4 fused pass on a half spectrum (the last
+    // axis index k3 in [0, N] is not folded).  tw_big: the 2L-point table.
+    int real_mode;
 };
 
 // ----------------------------------------------------- plan precompute ----

@@ -376,7 +376,9 @@ __device__ __forceinline__ void store_global(const cplx<R>* v, cplx<R>* __restri
 // Khat octant values for the thread's spectral positions (last-stage outputs
 // of plan P), loaded before the forward transform so that their latency hides
 // behind it; d == 3: column c = k2 * L + k3, d == 2: column c = k2.
-template <typename R, int L, int C, int NT, int MODE, RP P, int D, bool CPLX>
+// HALF: real-data plans keep the half spectrum k3 in [0, N] of the last axis;
+// the column is then c = k2 (N + 1) + k3 (3D) or c = k2 (2D), k3 / k2 unfolded.
+template <typename R, int L, int C, int NT, int MODE, RP P, int D, bool CPLX, bool HALF = false>
 __device__ __forceinline__ void table_fetch(cplx<R>* kt, const void* __restrict__ table, int tabN, int col0,
                                             int nvalid, int t) {
     constexpr int RAD = P.r[P.n - 1];
@@ -392,9 +394,14 @@ __device__ __forceinline__ void table_fetch(cplx<R>* kt, const void* __restrict_
         bmap<L, C, NT, MODE, RAD>(t, i, q, j);
         const int col = min(col0 + q, col0 + nvalid - 1);
         unsigned rowoff;
-        if constexpr (D == 3) {
+        if constexpr (D == 3 && HALF) {
+            const int k2 = col / N1, k3 = col - (col / N1) * N1;
+            rowoff = (unsigned)(min(k2, L - k2) * N1 + k3);
+        } else if constexpr (D == 3) {
             const int k2 = col / L, k3 = col % L;
             rowoff = (unsigned)(min(k2, L - k2) * N1 + min(k3, L - k3));
+        } else if constexpr (HALF) {
+            rowoff = (unsigned)col;
         } else {
             rowoff = (unsigned)min(col, L - col);
         }
@@ -420,7 +427,7 @@ __device__ __forceinline__ void table_fetch(cplx<R>* kt, const void* __restrict_
 
 // Four-step step B (2D): the spectral index along the axis is k = o + L1 e over
 // the whole axis length Lb; the column index folds over Lb as well.
-template <typename R, int L, int C, int NT, int MODE, RP P, bool CPLX>
+template <typename R, int L, int C, int NT, int MODE, RP P, bool CPLX, bool HALF = false>
 __device__ __forceinline__ void table_fetch_fs(cplx<R>* kt, const void* __restrict__ table, int tabN, int col0,
                                                int nvalid, int o, int L1, int Lb, int t) {
     constexpr int RAD = P.r[P.n - 1];
@@ -431,7 +438,7 @@ __device__ __forceinline__ void table_fetch_fs(cplx<R>* kt, const void* __restri
         int q, j;
         bmap<L, C, NT, MODE, RAD>(t, i, q, j);
         const int col = min(col0 + q, col0 + nvalid - 1);
-        const unsigned rowoff = (unsigned)min(col, Lb - col);
+        const unsigned rowoff = HALF ? (unsigned)col : (unsigned)min(col, Lb - col);
 #pragma unroll
         for (int r = 0; r < RAD; ++r) {
             const int k = o + L1 * (j + r * (L / RAD));
@@ -471,6 +478,95 @@ __device__ __forceinline__ void deriv_copy(const cplx<R>* v, cplx<R>* v2, R ks, 
             v2[i * RAD + r] = L1 ? ikap(v[i * RAD + r], o + L1 * e, Lb, ks) : ikap(v[i * RAD + r], e, L, ks);
         }
     }
+}
+
+// Real data (real_mode 1 and 2).  A real sequence x of length 2L is read as
+// z[m] = x[2m] + i x[2m+1], m < L; with Z = DFT_L(z) and W = e^{-2 pi i/(2L)},
+// its spectrum on k in [0, L] is
+//   X[k] = (Z[k] + conj Z[L-k])/2 - (i/2) W^k (Z[k] - conj Z[L-k])   (Z L-periodic),
+// and conversely the unnormalised inverse of X is recovered from the
+// unnormalised length-L inverse of
+//   Z'[k] = (X[k] + conj X[L-k]) + i W^-k (X[k] - conj X[L-k]),  k < L,
+// whose outputs are (x[2m], x[2m+1]) times 2L.
+
+// After a forward transform (ROW tiles, outputs of plan P in registers):
+// the L + 1 values X[k] of every valid pencil, stored with element stride se.
+template <typename R, int L, int C, int NT, RP P>
+__device__ __forceinline__ void r2c_store(const cplx<R>* v, cplx<R>* lds, cplx<R>* __restrict__ g, const FTile& tl,
+                                          long long se, int t, const cplx<R>* __restrict__ tw2) {
+    using LY = Lay<L, C, MODE_ROW, (int)sizeof(cplx<R>)>;
+    constexpr int RAD = P.r[P.n - 1];
+    constexpr int E = C * L / NT;
+    constexpr int LR = L / RAD;
+#pragma unroll
+    for (int i = 0; i < E / RAD; ++i) {
+        int q, j;
+        bmap<L, C, NT, MODE_ROW, RAD>(t, i, q, j);
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) lds[LY::idx(q, j + r * LR)] = v[i * RAD + r];
+    }
+    __syncthreads();
+    constexpr int NOUT = C * (L + 1), IT = (NOUT + NT - 1) / NT;
+    cplx<R>* __restrict__ gb = g + tl.out0;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int idx = t + it * NT;
+        const int q = idx / (L + 1), k = idx - q * (L + 1);
+        if (idx < NOUT && q < tl.nvalid) {
+            const cplx<R> a = lds[LY::idx(q, k == L ? 0 : k)];
+            const cplx<R> b = lds[LY::idx(q, k == 0 ? 0 : L - k)];
+            const cplx<R> sm = mk(a.x + b.x, a.y - b.y);  // a + conj b
+            const cplx<R> df = mk(a.x - b.x, a.y + b.y);  // a - conj b
+            const cplx<R> wd = cmul(tw2[k], df);
+            gb[(long long)q * tl.oq + (long long)k * se] = mk(R(0.5) * (sm.x + wd.y), R(0.5) * (sm.y - wd.x));
+        }
+    }
+}
+
+// Before an inverse transform (ROW tiles): the L + 1 inputs X[k] of every
+// pencil staged in LDS (q (L + 1) + k), then Z'[e] for this thread's stage-0
+// elements e of plan P.
+template <typename R, int L, int C, int NT, RP P>
+__device__ __forceinline__ void c2r_load(cplx<R>* v, cplx<R>* lds, const cplx<R>* __restrict__ g, const FTile& tl,
+                                         long long se, int t, const cplx<R>* __restrict__ tw2) {
+    constexpr int RAD = P.r[0];
+    constexpr int E = C * L / NT;
+    constexpr int LR = L / RAD;
+    constexpr int NIN = C * (L + 1), IT = (NIN + NT - 1) / NT;
+    constexpr int CHM = sizeof(R) == 8 ? 8 : 16;
+    constexpr int CH = IT < CHM ? IT : CHM;  // loads in flight per batch
+    const cplx<R>* __restrict__ gb = g + tl.in0;
+#pragma unroll
+    for (int i0 = 0; i0 < IT; i0 += CH) {
+        cplx<R> xin[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int idx = t + (i0 + c) * NT;
+            const int q = idx / (L + 1), k = idx - q * (L + 1);
+            const int qq = min(q, tl.nvalid - 1);
+            if (i0 + c < IT && idx < NIN) xin[c] = gb[(long long)qq * tl.iq + (long long)k * se];
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+            if (i0 + c < IT && t + (i0 + c) * NT < NIN) lds[t + (i0 + c) * NT] = xin[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < E / RAD; ++i) {
+        int q, j;
+        bmap<L, C, NT, MODE_ROW, RAD>(t, i, q, j);
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) {
+            const int e = j + r * LR;
+            const cplx<R> a = lds[q * (L + 1) + e];
+            const cplx<R> b = lds[q * (L + 1) + L - e];
+            const cplx<R> sm = mk(a.x + b.x, a.y - b.y);
+            const cplx<R> df = mk(a.x - b.x, a.y + b.y);
+            const cplx<R> cw = cmulc(df, tw2[e]);  // W^-e (a - conj b)
+            v[i * RAD + r] = mk(sm.x - cw.y, sm.y + cw.x);
+        }
+    }
+    __syncthreads();
 }
 
 enum FastKind : int {
@@ -515,8 +611,9 @@ struct Policy {
 template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX, int FS>
 __device__ __forceinline__ void tile_body(cplx<R>* v, cplx<R>* kt, cplx<R>* lds, const FTile& tl,
                                           const PassDesc& p, int t, const cplx<R>* tw) {
-    constexpr int NOUTI = FS == 2 ? L : L / 2;  // inverse outputs kept
-    constexpr int PTI = FS == 2 ? 2 : 0;        // post twiddle of inverse outputs
+    constexpr int FSB = FS & 7;
+    constexpr int NOUTI = FSB == 2 ? L : L / 2;  // inverse outputs kept
+    constexpr int PTI = FSB == 2 ? 2 : 0;        // post twiddle of inverse outputs
     constexpr RP F = make_plan(L, kMaxRad<R>);
     constexpr RP I = reversed(F);
     constexpr int E = C * L / NT;
@@ -524,9 +621,12 @@ __device__ __forceinline__ void tile_body(cplx<R>* v, cplx<R>* kt, cplx<R>* lds,
     cplx<R>* __restrict__ gout = reinterpret_cast<cplx<R>*>(p.out);
     cplx<R>* __restrict__ gout2 = reinterpret_cast<cplx<R>*>(p.out2);
     const R ks = (R)p.kscale;
-    if constexpr (FK == FK_FWD) {
+    if constexpr (FK == FK_FWD && FSB == 3) {
         run_from<R, L, C, NT, MODE, -1, F, 0, SP>(v, lds, t, tw);
-        store_global<R, L, C, NT, MODE, F, L, FS == 1 ? 1 : 0>(v, gout, tl, p.out_se, t, p.tw_big);
+        r2c_store<R, L, C, NT, F>(v, lds, gout, tl, p.out_se, t, reinterpret_cast<const cplx<R>*>(p.tw_big));
+    } else if constexpr (FK == FK_FWD) {
+        run_from<R, L, C, NT, MODE, -1, F, 0, SP>(v, lds, t, tw);
+        store_global<R, L, C, NT, MODE, F, L, FSB == 1 ? 1 : 0>(v, gout, tl, p.out_se, t, p.tw_big);
     } else if constexpr (FK == FK_INV || FK == FK_INV_DERIV) {
         if constexpr (FK == FK_INV_DERIV) {
             cplx<R> w[E];
@@ -548,7 +648,7 @@ __device__ __forceinline__ void tile_body(cplx<R>* v, cplx<R>* kt, cplx<R>* lds,
         run_from<R, L, C, NT, MODE, -1, F, 0, SP>(v, lds, t, tw);
         table_apply<R, E, CPLX>(v, kt);
         if constexpr (FK == FK_FUSED_DERIV) {
-            if constexpr (FS == 2) deriv_copy<R, L, C, NT, MODE, F.r[F.n - 1]>(v, v, ks, t, tl.o, p.fs_L1, p.L_big);
+            if constexpr (FSB == 2) deriv_copy<R, L, C, NT, MODE, F.r[F.n - 1]>(v, v, ks, t, tl.o, p.fs_L1, p.L_big);
             else deriv_copy<R, L, C, NT, MODE, F.r[F.n - 1]>(v, v, ks, t);
         }
         if constexpr (FK == FK_FUSED || FK == FK_FUSED_DERIV) {
@@ -556,7 +656,7 @@ __device__ __forceinline__ void tile_body(cplx<R>* v, cplx<R>* kt, cplx<R>* lds,
             store_global<R, L, C, NT, MODE, I, NOUTI, PTI>(v, gout, tl, p.out_se, t, p.tw_big);
         } else {
             cplx<R> w[E];
-            if constexpr (FS == 2) deriv_copy<R, L, C, NT, MODE, F.r[F.n - 1]>(v, w, ks, t, tl.o, p.fs_L1, p.L_big);
+            if constexpr (FSB == 2) deriv_copy<R, L, C, NT, MODE, F.r[F.n - 1]>(v, w, ks, t, tl.o, p.fs_L1, p.L_big);
             else deriv_copy<R, L, C, NT, MODE, F.r[F.n - 1]>(v, w, ks, t);
             run_from<R, L, C, NT, MODE, +1, I, 0, SP>(v, lds, t, tw);
             store_global<R, L, C, NT, MODE, I, NOUTI, PTI>(v, gout, tl, p.out_se, t, p.tw_big);
@@ -576,9 +676,13 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
     constexpr int E = C * L / NT;
     constexpr bool FL = KindIO<FK>::fwd_load;
     constexpr RP PL = FL ? F : I;
-    constexpr int NIN = (FL && FS != 2) ? L / 2 : L;
+    constexpr int FSB = FS & 7;
+    constexpr bool HALF = (FS & 8) != 0;
+    constexpr int NIN = (FL && FSB != 2) ? L / 2 : L;
     using LY = Lay<L, C, MODE, (int)sizeof(cplx<R>)>;
-    __shared__ cplx<R> lds[PO::split ? (LY::size + 1) / 2 : LY::size];
+    constexpr int NLDS0 = PO::split ? (LY::size + 1) / 2 : LY::size;
+    constexpr int NLDS = (FSB == 4 && C * (L + 1) > NLDS0) ? C * (L + 1) : NLDS0;
+    __shared__ cplx<R> lds[NLDS];
     __shared__ cplx<R> twl[PO::twl ? L : 1];
     const cplx<R>* __restrict__ tw = reinterpret_cast<const cplx<R>*>(p.tw);
     if constexpr (PO::twl) {
@@ -590,16 +694,22 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
     const int t = threadIdx.x;
     const FTile tl = fast_tile<C, MODE>(p, b);
     const cplx<R>* __restrict__ gin = reinterpret_cast<const cplx<R>*>(p.in);
-    cplx<R> vn[LoadSet<R, L, C, NT, PL, NIN>::NV];
     cplx<R> v[E];
     constexpr bool TAB = FK == FK_FUSED || FK == FK_FUSED_GRAD || FK == FK_FUSED_DERIV;
     cplx<R> kt[TAB ? E : 1];
-    issue_loads<R, L, C, NT, MODE, PL, NIN>(vn, gin, tl, p.in_se, t);
-    if constexpr (TAB && FS == 2)
-        table_fetch_fs<R, L, C, NT, MODE, F, CPLX>(kt, p.table, p.tabN, tl.col0, tl.nvalid, tl.o, p.fs_L1, p.L_big, t);
-    else if constexpr (TAB)
-        table_fetch<R, L, C, NT, MODE, F, D, CPLX>(kt, p.table, p.tabN, tl.col0, tl.nvalid, t);
-    expand<R, L, C, NT, PL, NIN>(v, vn);
+    if constexpr (FSB == 4) {
+        static_assert(MODE == MODE_ROW && FK == FK_INV, "real-output pre-processing is a row inverse");
+        c2r_load<R, L, C, NT, PL>(v, lds, gin, tl, p.in_se, t, reinterpret_cast<const cplx<R>*>(p.tw_big));
+    } else {
+        cplx<R> vn[LoadSet<R, L, C, NT, PL, NIN>::NV];
+        issue_loads<R, L, C, NT, MODE, PL, NIN>(vn, gin, tl, p.in_se, t);
+        if constexpr (TAB && FSB == 2)
+            table_fetch_fs<R, L, C, NT, MODE, F, CPLX, HALF>(kt, p.table, p.tabN, tl.col0, tl.nvalid, tl.o, p.fs_L1,
+                                                             p.L_big, t);
+        else if constexpr (TAB)
+            table_fetch<R, L, C, NT, MODE, F, D, CPLX, HALF>(kt, p.table, p.tabN, tl.col0, tl.nvalid, t);
+        expand<R, L, C, NT, PL, NIN>(v, vn);
+    }
     tile_body<R, L, C, NT, MODE, FK, D, CPLX, FS>(v, kt, lds, tl, p, t, tw);
 }
 
@@ -641,6 +751,22 @@ hipError_t launch_shape(const PassDesc& p, int kind, hipStream_t s, const GroupA
     if (nblocks <= 0) return hipSuccess;
     if (nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     const bool fused = kind == KIND_FUSED || kind == KIND_FUSED_GRAD || kind == KIND_FUSED_DERIV;
+    if (p.real_mode) {
+        // real-data variants: rows in and out of the half spectrum, and the
+        // fused pass on a half spectrum (apply only; real tables)
+        if constexpr (MODE == MODE_ROW) {
+            if (p.real_mode == 1 && kind == KIND_FWD) return launch_k<R, L, C, NT, MODE, FK_FWD, 3, false, 3, GROUP>(p, nblocks, s, ga);
+            if (p.real_mode == 2 && kind == KIND_INV) return launch_k<R, L, C, NT, MODE, FK_INV, 3, false, 4, GROUP>(p, nblocks, s, ga);
+        } else {
+            if (p.real_mode == 4 && kind == KIND_FUSED && !p.table_complex) {
+                if (p.fs_L1 && p.d == 2 && p.post_tw == 2)
+                    return launch_k<R, L, C, NT, MODE, FK_FUSED, 2, false, 2 | 8, GROUP>(p, nblocks, s, ga);
+                if (!p.fs_L1 && p.d == 3) return launch_k<R, L, C, NT, MODE, FK_FUSED, 3, false, 8, GROUP>(p, nblocks, s, ga);
+                if (!p.fs_L1 && p.d == 2) return launch_k<R, L, C, NT, MODE, FK_FUSED, 2, false, 8, GROUP>(p, nblocks, s, ga);
+            }
+        }
+        return hipErrorInvalidValue;
+    }
     if constexpr (MODE == MODE_ROW) {
         if (fused) return hipErrorInvalidValue;  // fused passes are column passes
     } else if (fused) {

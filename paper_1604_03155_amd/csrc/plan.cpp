@@ -315,6 +315,16 @@ int lds_buffers_generic(int kind) {
 int choose_C(const vg_plan* p, const PassStep& st, bool* specialised) {
     *specialised = false;
     const PassDesc& d = st.desc;
+    if (d.real_mode) {
+        // real-data variants exist for the specialised kernels only
+        const int fc = fast_pass_C(d.L, st.mode, p->fp64);
+        const bool rowm = st.mode == MODE_ROW;
+        if (fc > 0 && fast_pass_fits(d.L, st.mode, p->fp64, d.in_se, d.out_se, rowm ? d.in_so : 1, rowm ? d.out_so : 1)) {
+            *specialised = true;
+            return fc;
+        }
+        return 0;
+    }
     // the specialised kernels cover the four-step steps of column passes:
     // step A (forward + twiddle), step B (fused, full length) and A' (inverse)
     const bool four = d.post_tw != 0 || d.fs_L1 != 0;
@@ -354,9 +364,10 @@ PassDesc base_desc(const vg_plan* p, int L) {
 }
 
 PassStep row_step(const vg_plan* p, int kind, int in_buf, long long in_pitch, int n_in, int out_buf,
-                  long long out_pitch, int n_out, long long rows, const char* name, int out2_buf = BUF_NONE) {
+                  long long out_pitch, int n_out, long long rows, const char* name, int out2_buf = BUF_NONE,
+                  int L = 0) {
     PassStep s;
-    s.desc = base_desc(p, 2 * p->N);
+    s.desc = base_desc(p, L ? L : 2 * p->N);
     s.desc.in_so = in_pitch;
     s.desc.in_se = 1;
     s.desc.out_so = out_pitch;
@@ -563,8 +574,75 @@ vg_status build_programs(vg_plan* p, hipStream_t stream) {
             G.steps.push_back(row_step(p, KIND_INV, W1, RP, (int)L, BUF_GRAD0 + 0, N, (int)N, N, "g3_row_inv_d1"));
         }
     }
+    // Real densities with a real table (Laplace, biharmonic): the half
+    // spectrum k3 in [0, N] (H = N + 1 values) of the last axis.  A real row
+    // of N values is read as N/2 complex pairs, so the row passes are
+    // length-N transforms with R2C / C2R processing (real_mode 1, 2); the
+    // column passes and the fused pass run on H columns (real_mode 4).
+    Program& Rr = p->real_prog;
+    Rr.steps.clear();
+    if (!p->table_complex) {
+        const long long H = N + 1;
+        auto rrow = [&](int kind, int in_buf, long long ip, int nin, int out_buf, long long op, int nout, long long rows,
+                        const char* name, int mode) {
+            PassStep s = row_step(p, kind, in_buf, ip, nin, out_buf, op, nout, rows, name, BUF_NONE, (int)N);
+            s.desc.real_mode = mode;
+            s.desc.L_big = (int)L;
+            return s;
+        };
+        if (p->d == 3) {
+            const long long PLr = L * H + PAD;
+            set_ws(Rr, {(size_t)(N * N * H) * es, (size_t)(N * PLr) * es});
+            Rr.steps.push_back(rrow(KIND_FWD, BUF_F, N / 2, (int)(N / 2), W0, H, (int)H, N * N, "r1_row_r2c", 1));
+            Rr.steps.push_back(col_step(p, KIND_FWD, W0, N * H, H, (int)N, W1, PLr, H, (int)L, H, N, "r2_col_fwd"));
+            PassStep f = col_step(p, KIND_FUSED, W1, 0, PLr, (int)N, W1, 0, PLr, (int)N, L * H, 1, "r3_fused");
+            f.desc.real_mode = 4;
+            Rr.steps.push_back(f);
+            Rr.steps.push_back(col_step(p, KIND_INV, W1, PLr, H, (int)L, W0, N * H, H, (int)N, H, N, "r4_col_inv"));
+            Rr.steps.push_back(rrow(KIND_INV, W0, H, (int)H, BUF_PHI, N / 2, (int)(N / 2), N * N, "r5_row_c2r", 2));
+        } else {
+            const long long RPr = H + PAD;
+            PassStep f = col_step(p, KIND_FUSED, W0, 0, RPr, (int)N, W0, 0, RPr, (int)N, H, 1, "r2_fused");
+            f.desc.real_mode = 4;
+            bool spec = false;
+            if (choose_C(p, f, &spec) > 0) {
+                set_ws(Rr, {(size_t)(N * RPr) * es});
+                Rr.steps.push_back(rrow(KIND_FWD, BUF_F, N / 2, (int)(N / 2), W0, RPr, (int)H, N, "r1_row_r2c", 1));
+                Rr.steps.push_back(f);
+                Rr.steps.push_back(rrow(KIND_INV, W0, RPr, (int)H, BUF_PHI, N / 2, (int)(N / 2), N, "r3_row_c2r", 2));
+            } else {
+                // long columns: four steps as in the complex program, on H columns
+                const std::vector<int> splits = four_step_splits((int)L, p->fp64);
+                if (!splits.empty()) {
+                    int L1 = splits[0];
+                    if (p->cfg.fs_L1 && std::find(splits.begin(), splits.end(), p->cfg.fs_L1) != splits.end())
+                        L1 = p->cfg.fs_L1;
+                    const int L2 = (int)(L / L1);
+                    set_ws(Rr, {(size_t)(L * RPr) * es});
+                    auto sA = [&](int kind, const char* name) {
+                        PassStep s = col_step(p, kind, W0, RPr, (long long)L2 * RPr, kind == KIND_FWD ? L1 / 2 : L1, W0, RPr,
+                                              (long long)L2 * RPr, kind == KIND_FWD ? L1 : L1 / 2, H, L2, name, BUF_NONE, L1);
+                        s.desc.L_big = (int)L;
+                        s.desc.post_tw = kind == KIND_FWD ? 1 : 0;
+                        return s;
+                    };
+                    PassStep sB = col_step(p, KIND_FUSED, W0, (long long)L2 * RPr, RPr, L2, W0, (long long)L2 * RPr, RPr, L2,
+                                           H, L1, "r2b_fused", BUF_NONE, L2);
+                    sB.desc.L_big = (int)L;
+                    sB.desc.post_tw = 2;
+                    sB.desc.fs_L1 = L1;
+                    sB.desc.real_mode = 4;
+                    Rr.steps.push_back(rrow(KIND_FWD, BUF_F, N / 2, (int)(N / 2), W0, RPr, (int)H, N, "r1_row_r2c", 1));
+                    Rr.steps.push_back(sA(KIND_FWD, "r2a_col_fwd"));
+                    Rr.steps.push_back(sB);
+                    Rr.steps.push_back(sA(KIND_INV, "r2c_col_inv"));
+                    Rr.steps.push_back(rrow(KIND_INV, W0, RPr, (int)H, BUF_PHI, N / 2, (int)(N / 2), N, "r3_row_c2r", 2));
+                }
+            }
+        }
+    }
     // twiddles, tile widths and support check for every step
-    for (Program* pr : {&A, &G}) {
+    for (Program* pr : {&A, &G, &Rr}) {
         for (PassStep& st : pr->steps) {
             vg_status s2 = twiddle_table(p, st.desc.L, stream);
             if (s2 != VG_OK) return s2;
@@ -578,6 +656,13 @@ vg_status build_programs(vg_plan* p, hipStream_t stream) {
             bool spec = false;
             st.desc.C = choose_C(p, st, &spec);
             st.desc.specialised = spec ? 1 : 0;
+            if (st.desc.C == 0 && pr == &Rr) {
+                // no real-data variant for this length: real applies unsupported
+                Rr.steps.clear();
+                Rr.ws_offsets.clear();
+                Rr.ws_bytes = 0;
+                break;
+            }
             if (st.desc.C == 0) return fail(VG_ERR_UNSUPPORTED_SIZE, std::string("pass ") + st.name + ": pencil does not fit in LDS");
         }
     }
@@ -600,7 +685,7 @@ double pass_bytes(const vg_plan* p, const PassStep& s) {
 }  // namespace
 
 void finalize_bytes(vg_plan* p) {
-    for (Program* pr : {&p->apply_prog, &p->grad_prog})
+    for (Program* pr : {&p->apply_prog, &p->grad_prog, &p->real_prog})
         for (PassStep& s : pr->steps) s.bytes = pass_bytes(p, s);
 }
 

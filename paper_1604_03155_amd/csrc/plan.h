@@ -69,6 +69,7 @@ struct vg_plan {
     void* T_dev = nullptr;        // device, N^d complex128 (keep_operator)
     double precompute_ms = 0.0;
     vg::Program apply_prog, grad_prog;
+    vg::Program real_prog;   // real densities with a real kernel (Laplace, biharmonic); empty if unsupported
     // internal workspace for calls with workspace == NULL
     mutable std::mutex ws_mutex;
     mutable void* internal_ws = nullptr;
