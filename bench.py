@@ -15,6 +15,8 @@ roofline: the pass with the largest device time, its algorithmic bytes per
 launch divided by its average launch time (HIP events recorded between passes
 on the apply stream during the timed region), against 8 TB/s.
 cpu_baseline: the FP64 oracle's apply on the host cores, same workload.
+fp64_gpu: the FP64 GPU path (complex128 end to end) on the same density, its
+time per apply, accuracy against the oracle and the FP32 path's speedup.
 """
 from __future__ import annotations
 
@@ -70,6 +72,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=20,
                     help="oracle applies timed for cpu_baseline (0: skip); 20 is about 10 s on 16 host threads")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--fp64-steps", type=int, default=10,
+                    help="timed applies of the FP64 GPU path on the same density (0: skip)")
     ap.add_argument("--hbm-copy-mib", type=int, default=0,
                     help="after timing, run one streaming copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -114,6 +118,26 @@ def main():
     ms_per_step = 1e3 * seconds / args.steps
     value = V * args.steps / seconds
     log(f"[bench] {ms_per_step:.3f} ms/step, {value:.3e} grid pts/s")
+
+    # the plain FP64 single-density GPU path on the same density, for the
+    # FP32 speedup at the stated accuracy
+    fp64 = None
+    if args.fp64_steps > 0:
+        plan64 = vg.Plan(d, N, kernel, k, precision="fp64")
+        x64 = torch.from_numpy(f64).cuda()
+        out64 = torch.empty_like(x64)
+        ws64 = plan64.new_workspace()
+        plan64.apply(x64, out=out64, workspace=ws64)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter()
+        for _ in range(args.fp64_steps):
+            plan64.apply(x64, out=out64, workspace=ws64)
+        torch.cuda.synchronize()
+        ms64 = 1e3 * (time.perf_counter() - t64) / args.fp64_steps
+        fp64 = {"ms_per_step": round(ms64, 4), "value": V / (ms64 * 1e-3),
+                "fp32_speedup": round(ms64 / ms_per_step, 3), "steps": args.fp64_steps}
+        log(f"[bench] FP64 GPU path {ms64:.3f} ms/step; FP32 speedup {ms64 / ms_per_step:.2f}x")
+        del plan64, ws64
 
     if args.hbm_copy_mib > 0:
         nb = args.hbm_copy_mib << 20
@@ -166,6 +190,8 @@ def main():
         "plan_ms": round(plan_ms, 3),
         "roofline": roofline,
     }
+    if fp64 is not None:
+        result["fp64_gpu"] = fp64
 
     if not args.no_parity or args.cpu_sample > 0:
         from oracle import operator as op
@@ -178,6 +204,10 @@ def main():
             result["rel_l2"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
             result["rel_max"] = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
             log(f"[bench] rel L2 vs FP64 oracle {result['rel_l2']:.2e}")
+            if fp64 is not None:
+                g64 = out64.cpu().numpy()
+                fp64["rel_l2"] = float(np.linalg.norm(g64 - ref) / np.linalg.norm(ref))
+                log(f"[bench] FP64 GPU path rel L2 vs oracle {fp64['rel_l2']:.2e}")
         if args.cpu_sample > 0:
             threads = op._workers()
             tc = time.perf_counter()
