@@ -74,9 +74,20 @@ def lattice_radius(d, M, P=P_DEFAULT):
     return np.sqrt(sq)
 
 
-def kernel_spectrum(d, N, kernel, k=0.0, L=None, P=P_DEFAULT):
-    """G^L(|s_m|) on the full (P N)^d lattice (Section 2, Tables 1-2)."""
+def kernel_spectrum(d, N, kernel, k=0.0, L=None, P=P_DEFAULT, h=None):
+    """G^L(|s_m|) on the full (P N)^d lattice (Section 2, Tables 1-2).  For the
+    convection kernel (Tables 1-2, last row) G_h(s) = G^L_{|h|}(|s - h|), the
+    Helmholtz transform at the shifted frequency, which is not radial."""
     M = P * N
+    if kernel == "convection":
+        h = np.asarray(h, dtype=np.float64)
+        m = signed_index(M) * (2.0 * math.pi / P)
+        sq = np.zeros((M,) * d)
+        for ax in range(d):
+            shape = [1] * d
+            shape[ax] = M
+            sq = sq + ((m - h[ax]) ** 2).reshape(shape)
+        return greens.kernel_transform(d, "helmholtz", np.sqrt(sq), float(np.linalg.norm(h)), L)
     return greens.kernel_transform(d, kernel, lattice_radius(d, M, P), k, L)
 
 
@@ -274,11 +285,23 @@ class Plan:
     route='full' builds (1) and (2) with full-lattice FFTs (small N);
     route='octant' uses the cosine forms (any N that fits in memory)."""
 
-    def __init__(self, d, N, kernel, k=0.0, L=None, P=P_DEFAULT, route=None):
+    def __init__(self, d, N, kernel, k=0.0, L=None, P=P_DEFAULT, route=None, h=None):
         if N % 2 or N < 2:
             raise ValueError("N must be even and >= 2")
         self.d, self.N, self.kernel, self.k, self.P = d, N, kernel, float(k), P
         self.L = greens.L_DEFAULT[d] if L is None else L
+        if kernel == "convection":
+            # no per-axis symmetry: T on all offsets |n_j| <= N-1 and the full
+            # (2N)^d Khat, from full-lattice FFTs
+            self.h = np.asarray(h, dtype=np.float64)
+            self.k = float(np.linalg.norm(self.h))
+            self.route = "full"
+            self.Ghat = kernel_spectrum(d, N, kernel, 0.0, self.L, P, self.h)
+            self.T_off = operator_T(self.Ghat, N)
+            self.Khat = kernel_hat_2n(self.T_off, N)
+            self.T_oct = None
+            self.K_oct = None
+            return
         if route is None:
             route = "full" if (P * N) ** d <= 2 ** 24 else "octant"
         self.route = route

@@ -246,3 +246,43 @@ def test_pde_residual_on_the_box(d, kernel, k, N):
     # |kappa|^4 ~ 5e9 (N = 48); a wrong sign or factor leaves an O(1) residual
     bound = 1e-8 if kernel in ("biharmonic", "laplace_helmholtz") else 1e-12
     assert np.linalg.norm(res) / np.linalg.norm(f) < bound
+
+
+# ----------------------------------------------- convection kernel (h.grad) --
+
+@pytest.mark.parametrize("d,N,h", [(2, 48, (3.3, -1.7)), (2, 48, (12.0, 5.0)), (3, 48, (2.5, -1.0, 4.0))])
+def test_convection_kernel_pde_residual(d, N, h):
+    """Tables 1-2, last row: G_h(s) = G_{|h|}(|s - h|) is the transform of
+    g_h(x) = e^{i h.x} g_{|h|}(|x|), which satisfies (Delta - 2i h.grad) g_h =
+    -delta; phi = g_h * f is checked spectrally on the box."""
+    sigma = 0.05
+    _, f = _centered_gaussian(d, N, sigma)
+    plan = op.Plan(d, N, "convection", h=h)
+    spec = plan.Khat * op.fftn(op.pad(f, 2 * N))
+    kap = math.pi * op.signed_index(2 * N)
+    ks = [kap.reshape([-1 if a == b else 1 for b in range(d)]) for a in range(d)]
+    Lop = -sum(kk ** 2 for kk in ks) + 2.0 * sum(hh * kk for hh, kk in zip(h, ks))
+    res = op.crop(op.ifftn(Lop * spec), N) + f
+    assert np.linalg.norm(res) / np.linalg.norm(f) < 1e-11
+
+
+@pytest.mark.parametrize("d,N,h", [(2, 8, (2.0, -3.5)), (3, 4, (1.5, 0.5, -2.0))])
+def test_convection_T_naive_sum_routes_and_direct_summation(d, N, h):
+    rng = np.random.default_rng(11)
+    plan = op.Plan(d, N, "convection", h=h)
+    M = 4 * N
+    m = op.signed_index(M) * (2 * math.pi / 4)
+    grids = np.meshgrid(*([m] * d), indexing="ij")
+    G = greens.kernel_transform(d, "helmholtz", np.sqrt(sum((g - hh) ** 2 for g, hh in zip(grids, h))),
+                                float(np.linalg.norm(h)))
+    mi = np.meshgrid(*([op.signed_index(M)] * d), indexing="ij")
+    for n in [(0,) * d, (1,) + (0,) * (d - 1), tuple(range(-1, d - 1)), (N - 1,) * d, (-(N - 1),) * d]:
+        ref = np.sum(G * np.exp(2j * math.pi * sum(g * nn for g, nn in zip(mi, n)) / M)) / M ** d
+        got = plan.T_off[tuple(v + N - 1 for v in n)]
+        assert abs(got - ref) < 1e-14 * np.abs(plan.T_off).max()
+    f = _random_density(rng, d, N)
+    a = plan.apply(f)
+    assert np.linalg.norm(a - op.apply_4n(f, plan.Ghat)) / np.linalg.norm(a) < 1e-13
+    assert np.linalg.norm(a - op.apply_direct(f, plan.T_off)) / np.linalg.norm(a) < 1e-13
+    # not even: T(n) != T(-n) in general
+    assert abs(plan.T_off[(N,) * d] - plan.T_off[(N - 2,) * d]) > 1e-6 * np.abs(plan.T_off).max()
