@@ -60,13 +60,15 @@ typedef enum vg_status {
 } vg_status;
 
 /* The kernels of Tables 1 (3D) and 2 (2D), with the tables' Green's functions
- * (each satisfies L g = -delta for its operator L, except the last, whose
- * tabulated g_k - g_0 satisfies Delta(Delta + k^2) g = k^2 delta). */
+ * (each satisfies L g = -delta for its operator L, except Delta(Delta + k^2),
+ * whose tabulated g_k - g_0 satisfies Delta(Delta + k^2) g = k^2 delta). */
 typedef enum vg_kernel {
     VG_LAPLACE = 0,           /* Delta:        1/(4 pi r) (3D),  -(1/2 pi) log r (2D) */
     VG_HELMHOLTZ = 1,         /* Delta + k^2:  e^{ikr}/(4 pi r) (3D), (i/4) H_0^(1)(kr) (2D) */
     VG_BIHARMONIC = 2,        /* Delta^2:      r/(8 pi) (3D), -(r^2/(8 pi))(log r - 1) (2D) */
-    VG_LAPLACE_HELMHOLTZ = 3  /* Delta (Delta + k^2): g_k - g_0, the difference of the two above */
+    VG_LAPLACE_HELMHOLTZ = 3, /* Delta (Delta + k^2): g_k - g_0, the difference of the two above */
+    VG_CONVECTION = 4         /* Delta - 2i h.grad (vector h = opts.h, |h| > 0): e^{i h.x} g_{|h|}(x);
+                               * truncated transform G^L_{|h|}(|s - h|), not radial (Tables 1-2) */
 } vg_kernel;
 
 typedef enum vg_precision {
@@ -96,6 +98,7 @@ typedef struct vg_plan_opts {
     int tune;            /* vg_tune_mode, default VG_TUNE_OFF */
     int keep_operator;   /* nonzero: keep T (FP64) on the device for vg_plan_operator_entries */
     void* stream;        /* hipStream_t for the precompute, NULL = null stream */
+    double h[3];         /* VG_CONVECTION: the vector h (h[2] unused in 2D); ignored by the other kernels */
 } vg_plan_opts;
 
 /* Plan description returned by vg_plan_get_info. */
@@ -121,6 +124,11 @@ typedef struct vg_plan_info {
 /*
  * Create a plan for d in {2, 3}, even N >= 4 and a vg_kernel.  VG_HELMHOLTZ
  * and VG_LAPLACE_HELMHOLTZ need a finite k > 0 (the others ignore k).
+ * VG_CONVECTION needs opts with a finite h of |h| > 0 and ignores k (the
+ * plan's k is |h|); its kernel is not symmetric per axis, so the plan keeps
+ * the whole (2N)^d spectrum (complex, at most 4 GiB) instead of an octant,
+ * and its precompute takes full-lattice sums ((P N)^d evaluations of the
+ * transform); 3D plans of it are limited to N <= 256.
  * Runs the FP64 precompute of Sections 2 and 4 on the current device and
  * synchronises before returning.
  * Errors: VG_ERR_INVALID_ARG (bad arguments; *out untouched),
@@ -247,9 +255,11 @@ vg_status vg_ls_solve(const vg_plan* plan, const void* q, const void* phi_in, vo
  *   vg_plan_kernel_hat: Khat(m) on the octant m in [0, N]^d, (N+1)^d values,
  *     C order: the spectrum of T on the (2N)^d box (Khat(m) = Khat(2N - m)
  *     per axis), as stored for applies (FP32 plans: rounded to float).
+ *     VG_CONVECTION: all of m in [0, 2N)^d, (2N)^d values.
  *   vg_plan_operator_entries: T(n) on n in [0, N)^d, N^d values (T(n) = T(|n|)
  *     per axis); the entries of the high-order Nystrom matrix (Section 4
- *     remark).  Needs opts.keep_operator; VG_ERR_INVALID_ARG otherwise.
+ *     remark).  VG_CONVECTION: n in [-(N-1), N-1]^d, (2N-1)^d values, C order
+ *     of n + N - 1.  Needs opts.keep_operator; VG_ERR_INVALID_ARG otherwise.
  * host_out must hold the stated number of complex128 values.
  */
 vg_status vg_plan_kernel_hat(const vg_plan* plan, double* host_out);

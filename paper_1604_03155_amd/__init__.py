@@ -23,10 +23,11 @@ __all__ = [
 
 LIBRARY_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvgconv.so")
 
-LAPLACE, HELMHOLTZ, BIHARMONIC, LAPLACE_HELMHOLTZ = 0, 1, 2, 3
+LAPLACE, HELMHOLTZ, BIHARMONIC, LAPLACE_HELMHOLTZ, CONVECTION = 0, 1, 2, 3, 4
 FP32, FP64 = 0, 1
 _TUNE = {"off": 0, "quick": 1, "full": 2}
-_KERNELS = {"laplace": LAPLACE, "helmholtz": HELMHOLTZ, "biharmonic": BIHARMONIC, "laplace_helmholtz": LAPLACE_HELMHOLTZ}
+_KERNELS = {"laplace": LAPLACE, "helmholtz": HELMHOLTZ, "biharmonic": BIHARMONIC, "laplace_helmholtz": LAPLACE_HELMHOLTZ,
+            "convection": CONVECTION}
 
 if not os.path.exists(LIBRARY_PATH):
     raise ImportError(f"{LIBRARY_PATH} is missing: build it with `python paper_1604_03155_amd/build.py`")
@@ -36,7 +37,8 @@ _lib = ctypes.CDLL(LIBRARY_PATH)
 
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("L", ctypes.c_double), ("P", ctypes.c_int),
-                ("tune", ctypes.c_int), ("keep_operator", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("tune", ctypes.c_int), ("keep_operator", ctypes.c_int), ("stream", ctypes.c_void_p),
+                ("h", ctypes.c_double * 3)]
 
 
 class _Info(ctypes.Structure):
@@ -127,19 +129,28 @@ class Plan:
 
     d: 2 or 3; N: even points per side (h = 1/N); kernel: 'laplace',
     'helmholtz' (wavenumber k > 0), 'biharmonic' or 'laplace_helmholtz'
-    (Delta (Delta + k^2), kernel g_k - g_0, k > 0) (Tables 1-2); precision: 'fp32' (complex64 data, tables
+    (Delta (Delta + k^2), kernel g_k - g_0, k > 0) or 'convection' (Delta -
+    2i h.grad for the vector h, |h| > 0; k is ignored and set to |h|) (Tables
+    1-2); precision: 'fp32' (complex64 data, tables
     built in FP64 and rounded once) or 'fp64'.  L and P default to the paper's
     truncation radius (1.8 in 3D, 1.5 in 2D) and 4-fold oversampling."""
 
     def __init__(self, d, N, kernel="laplace", k=0.0, precision="fp32", L=None, P=None, tune="off",
-                 keep_operator=False, stream=None):
+                 keep_operator=False, stream=None, h=None):
         torch = _torch()
         self.d, self.N, self.kernel, self.k = int(d), int(N), kernel, float(k)
         self.precision = precision
         self._h = None
+        hv = [0.0, 0.0, 0.0]
+        if h is not None:
+            hl = [float(x) for x in h]
+            if len(hl) != self.d:
+                raise ValueError(f"h must have {self.d} components")
+            hv[:self.d] = hl
         opts = _Opts(FP64 if precision == "fp64" else FP32, float(L or 0.0), int(P or 0), _TUNE[tune],
                      1 if keep_operator else 0,
-                     stream.cuda_stream if stream is not None else torch.cuda.current_stream().cuda_stream)
+                     stream.cuda_stream if stream is not None else torch.cuda.current_stream().cuda_stream,
+                     (ctypes.c_double * 3)(*hv))
         h = _vp()
         _check(_lib.vg_plan_create_ex(self.d, self.N, _KERNELS[kernel], self.k, ctypes.byref(opts), ctypes.byref(h)),
                "vg_plan_create_ex")
@@ -148,6 +159,7 @@ class Plan:
         _check(_lib.vg_plan_get_info(h, ctypes.byref(info)), "vg_plan_get_info")
         self.info = {f: getattr(info, f) for f, _ in _Info._fields_}
         self.dtype = torch.complex128 if precision == "fp64" else torch.complex64
+        self.k = self.info["k"]
 
     # -- housekeeping ------------------------------------------------------
     def close(self):
@@ -254,16 +266,20 @@ class Plan:
         return int(_lib.vg_ls_workspace_size(self._h))
 
     def kernel_hat(self):
-        """Khat on the octant [0, N]^d as complex128 numpy (Section 4)."""
+        """Khat on the octant [0, N]^d as complex128 numpy (Section 4); the
+        convection kernel: on the whole box [0, 2N)^d."""
         import numpy as np
-        out = np.empty((self.N + 1,) * self.d, dtype=np.complex128)
+        n = 2 * self.N if self.kernel == "convection" else self.N + 1
+        out = np.empty((n,) * self.d, dtype=np.complex128)
         _check(_lib.vg_plan_kernel_hat(self._h, _vp(out.ctypes.data)), "vg_plan_kernel_hat")
         return out
 
     def operator_entries(self):
-        """T(n) on the octant [0, N)^d as complex128 numpy (needs keep_operator)."""
+        """T(n) on the octant [0, N)^d as complex128 numpy (needs keep_operator);
+        the convection kernel: on all offsets |n_j| <= N - 1, index n + N - 1."""
         import numpy as np
-        out = np.empty((self.N,) * self.d, dtype=np.complex128)
+        n = 2 * self.N - 1 if self.kernel == "convection" else self.N
+        out = np.empty((n,) * self.d, dtype=np.complex128)
         _check(_lib.vg_plan_operator_entries(self._h, _vp(out.ctypes.data)), "vg_plan_operator_entries")
         return out
 

@@ -86,14 +86,32 @@ vg_status vg_plan_create_ex(int d, int N, vg_kernel kernel, double k, const vg_p
         *out = nullptr;
         if (d != 2 && d != 3) return fail(VG_ERR_INVALID_ARG, "d must be 2 or 3");
         if (N < 4 || (N % 2)) return fail(VG_ERR_INVALID_ARG, "N must be even and at least 4");
-        if (kernel != VG_LAPLACE && kernel != VG_HELMHOLTZ && kernel != VG_BIHARMONIC && kernel != VG_LAPLACE_HELMHOLTZ)
+        if (kernel != VG_LAPLACE && kernel != VG_HELMHOLTZ && kernel != VG_BIHARMONIC &&
+            kernel != VG_LAPLACE_HELMHOLTZ && kernel != VG_CONVECTION)
             return fail(VG_ERR_INVALID_ARG, "unknown kernel");
         const bool helm = kernel == VG_HELMHOLTZ || kernel == VG_LAPLACE_HELMHOLTZ;
+        const bool conv = kernel == VG_CONVECTION;
         if (helm && !(std::isfinite(k) && k > 0.0))
             return fail(VG_ERR_INVALID_ARG, "Helmholtz needs a finite k > 0");
         vg_plan_opts o;
         std::memset(&o, 0, sizeof(o));
         if (opts) o = *opts;
+        double hvec[3] = {0.0, 0.0, 0.0}, hnorm = 0.0;
+        if (conv) {
+            bool finite = true;
+            for (int i = 0; i < d; ++i) {
+                hvec[i] = o.h[i];
+                finite = finite && std::isfinite(hvec[i]);
+                hnorm += hvec[i] * hvec[i];
+            }
+            hnorm = std::sqrt(hnorm);
+            if (!finite || !(hnorm > 0.0) || !std::isfinite(hnorm))
+                return fail(VG_ERR_INVALID_ARG, "the convection kernel needs a finite vector h with |h| > 0");
+            if (d == 3 && N > 256) return fail(VG_ERR_UNSUPPORTED_SIZE, "3D convection plans need N <= 256");
+            double tb = (o.precision == VG_FP64) ? 16.0 : 8.0;
+            for (int i = 0; i < d; ++i) tb *= 2.0 * N;
+            if (tb > 4294967296.0) return fail(VG_ERR_UNSUPPORTED_SIZE, "convection table above 4 GiB");
+        }
         if (o.precision != VG_FP32 && o.precision != VG_FP64) return fail(VG_ERR_INVALID_ARG, "unknown precision");
         const double L = (o.L == 0.0) ? (d == 3 ? 1.8 : 1.5) : o.L;
         if (!(std::isfinite(L) && L > std::sqrt((double)d)))
@@ -115,14 +133,15 @@ vg_status vg_plan_create_ex(int d, int N, vg_kernel kernel, double k, const vg_p
         p->d = d;
         p->N = N;
         p->kernel = kernel;
-        p->k = helm ? k : 0.0;
+        p->k = helm ? k : (conv ? hnorm : 0.0);
+        for (int i = 0; i < 3; ++i) p->h[i] = hvec[i];
         p->L = L;
         p->P = P;
         p->precision = o.precision;
         p->fp64 = o.precision == VG_FP64;
         p->tune = o.tune;
         p->radices = rad;
-        p->table_complex = helm ? 1 : 0;
+        p->table_complex = (helm || conv) ? 1 : 0;
         hipError_t he = hipGetDevice(&p->device);
         if (he != hipSuccess) return from_hip(he, "hipGetDevice");
         hipStream_t s = reinterpret_cast<hipStream_t>(o.stream);
@@ -243,7 +262,7 @@ vg_status vg_plan_kernel_hat(const vg_plan* p, double* host_out) {
     return guarded([&]() -> vg_status {
         if (!p || !host_out) return fail(VG_ERR_INVALID_ARG, "NULL argument");
         long long n = 1;
-        for (int i = 0; i < p->d; ++i) n *= (p->N + 1);
+        for (int i = 0; i < p->d; ++i) n *= (p->kernel == VG_CONVECTION ? 2 * p->N : p->N + 1);
         std::vector<unsigned char> h(p->table_bytes);
         hipError_t e = hipMemcpy(h.data(), p->table, p->table_bytes, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return from_hip(e, "table download");
@@ -271,7 +290,7 @@ vg_status vg_plan_operator_entries(const vg_plan* p, double* host_out) {
     if (!p || !host_out) return fail(VG_ERR_INVALID_ARG, "NULL argument");
     if (!p->T_dev) return fail(VG_ERR_INVALID_ARG, "plan was created without keep_operator");
     long long n = 1;
-    for (int i = 0; i < p->d; ++i) n *= p->N;
+    for (int i = 0; i < p->d; ++i) n *= (p->kernel == VG_CONVECTION ? 2 * p->N - 1 : p->N);
     return from_hip(hipMemcpy(host_out, p->T_dev, (size_t)n * 16, hipMemcpyDeviceToHost), "operator download");
 }
 

@@ -78,7 +78,7 @@ bool env_flag(const char* name) {
 using GroupKey = std::tuple<int, int, int, int, int, int, int, int, int>;
 GroupKey key_of(const BoundStep& b) {
     const bool fused = b.kind == KIND_FUSED || b.kind == KIND_FUSED_GRAD || b.kind == KIND_FUSED_DERIV;
-    return GroupKey(b.desc.L, b.mode, b.kind, b.desc.C, fused ? b.desc.d : 0, fused ? b.desc.table_complex : 0,
+    return GroupKey(b.desc.L, b.mode, b.kind, b.desc.C, fused ? b.desc.d : 0, fused ? b.desc.table_complex | (b.desc.table_full << 1) : 0,
                     b.desc.post_tw, b.desc.fs_L1 != 0 ? 1 : 0, b.desc.specialised);
 }
 

@@ -104,6 +104,9 @@ struct PassDesc {
     // written as L complex pairs); 4 fused pass on a half spectrum (the last
     // axis index k3 in [0, N] is not folded).  tw_big: the 2L-point table.
     int real_mode;
+    // 1: the table covers every spectral index of the L^d box (no octant
+    // fold): flat = k * L^(d-1) + column (convection kernel)
+    int table_full;
 };
 
 // ----------------------------------------------------- plan precompute ----
@@ -118,6 +121,11 @@ struct GreensParams {
     int ntaylor;
     double taylor_r[10], taylor_i[10];
     double window;
+    // full-lattice generator (convection kernel): lattice of M points per axis
+    // in FFT order, G evaluated at |s_m - h| (with kernel = Helmholtz, k = |h|)
+    int full;
+    int M;
+    double h[3];
 };
 
 // Grouped launch of one specialised pass over several arrays: device arrays
@@ -148,5 +156,10 @@ hipError_t launch_cos_contract(const c64* in, c64* out, const double* cmat, long
                                int Nout, long long I, hipStream_t s);
 hipError_t launch_round_table(const c64* in, void* out, long long n, int to_fp32, int complex_out,
                               hipStream_t s);
+// First contraction on the full lattice (g.full): rows = M^(d-1), K = M.
+hipError_t launch_greens_contract_full(const GreensParams& g, int n_out, const double* cmat, c64* out,
+                                       hipStream_t s);
+// out[i] = a[i] + sign * i * b[i]
+hipError_t launch_combine(const c64* a, const c64* b, c64* out, long long n, int sign, hipStream_t s);
 
 }  // namespace vg

@@ -378,11 +378,28 @@ __device__ __forceinline__ void store_global(const cplx<R>* v, cplx<R>* __restri
 // behind it; d == 3: column c = k2 * L + k3, d == 2: column c = k2.
 // HALF: real-data plans keep the half spectrum k3 in [0, N] of the last axis;
 // the column is then c = k2 (N + 1) + k3 (3D) or c = k2 (2D), k3 / k2 unfolded.
-template <typename R, int L, int C, int NT, int MODE, RP P, int D, bool CPLX, bool HALF = false>
+// FULL: the table holds every spectral index (convection kernel): flat =
+// e L^(d-1) + c.
+template <typename R, int L, int C, int NT, int MODE, RP P, int D, bool CPLX, bool HALF = false, bool FULL = false>
 __device__ __forceinline__ void table_fetch(cplx<R>* kt, const void* __restrict__ table, int tabN, int col0,
                                             int nvalid, int t) {
     constexpr int RAD = P.r[P.n - 1];
     constexpr int E = C * L / NT;
+    if constexpr (FULL) {
+        constexpr unsigned plane = D == 3 ? (unsigned)L * (unsigned)L : (unsigned)L;
+#pragma unroll
+        for (int i = 0; i < E / RAD; ++i) {
+            int q, j;
+            bmap<L, C, NT, MODE, RAD>(t, i, q, j);
+            const unsigned col = (unsigned)min(col0 + q, col0 + nvalid - 1);
+#pragma unroll
+            for (int r = 0; r < RAD; ++r) {
+                const unsigned flat = (unsigned)(j + r * (L / RAD)) * plane + col;
+                kt[i * RAD + r] = ld_off<cplx<R>>(table, flat * (unsigned)sizeof(cplx<R>));
+            }
+        }
+        return;
+    }
     const int N1 = tabN + 1;
     // block strides as opaque scalars: per element one add, no multiply
     const unsigned plane = uniform_u32((D == 3) ? (unsigned)(N1 * N1) : (unsigned)N1);
@@ -427,11 +444,25 @@ __device__ __forceinline__ void table_fetch(cplx<R>* kt, const void* __restrict_
 
 // Four-step step B (2D): the spectral index along the axis is k = o + L1 e over
 // the whole axis length Lb; the column index folds over Lb as well.
-template <typename R, int L, int C, int NT, int MODE, RP P, bool CPLX, bool HALF = false>
+template <typename R, int L, int C, int NT, int MODE, RP P, bool CPLX, bool HALF = false, bool FULL = false>
 __device__ __forceinline__ void table_fetch_fs(cplx<R>* kt, const void* __restrict__ table, int tabN, int col0,
                                                int nvalid, int o, int L1, int Lb, int t) {
     constexpr int RAD = P.r[P.n - 1];
     constexpr int E = C * L / NT;
+    if constexpr (FULL) {
+#pragma unroll
+        for (int i = 0; i < E / RAD; ++i) {
+            int q, j;
+            bmap<L, C, NT, MODE, RAD>(t, i, q, j);
+            const unsigned col = (unsigned)min(col0 + q, col0 + nvalid - 1);
+#pragma unroll
+            for (int r = 0; r < RAD; ++r) {
+                const unsigned flat = (unsigned)(o + L1 * (j + r * (L / RAD))) * (unsigned)Lb + col;
+                kt[i * RAD + r] = ld_off<cplx<R>>(table, flat * (unsigned)sizeof(cplx<R>));
+            }
+        }
+        return;
+    }
     const int N1 = tabN + 1;
 #pragma unroll
     for (int i = 0; i < E / RAD; ++i) {
@@ -678,6 +709,7 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
     constexpr RP PL = FL ? F : I;
     constexpr int FSB = FS & 7;
     constexpr bool HALF = (FS & 8) != 0;
+    constexpr bool FULL = (FS & 16) != 0;
     constexpr int NIN = (FL && FSB != 2) ? L / 2 : L;
     using LY = Lay<L, C, MODE, (int)sizeof(cplx<R>)>;
     constexpr int NLDS0 = PO::split ? (LY::size + 1) / 2 : LY::size;
@@ -704,10 +736,10 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
         cplx<R> vn[LoadSet<R, L, C, NT, PL, NIN>::NV];
         issue_loads<R, L, C, NT, MODE, PL, NIN>(vn, gin, tl, p.in_se, t);
         if constexpr (TAB && FSB == 2)
-            table_fetch_fs<R, L, C, NT, MODE, F, CPLX, HALF>(kt, p.table, p.tabN, tl.col0, tl.nvalid, tl.o, p.fs_L1,
-                                                             p.L_big, t);
+            table_fetch_fs<R, L, C, NT, MODE, F, CPLX, HALF, FULL>(kt, p.table, p.tabN, tl.col0, tl.nvalid, tl.o,
+                                                                   p.fs_L1, p.L_big, t);
         else if constexpr (TAB)
-            table_fetch<R, L, C, NT, MODE, F, D, CPLX, HALF>(kt, p.table, p.tabN, tl.col0, tl.nvalid, t);
+            table_fetch<R, L, C, NT, MODE, F, D, CPLX, HALF, FULL>(kt, p.table, p.tabN, tl.col0, tl.nvalid, t);
         expand<R, L, C, NT, PL, NIN>(v, vn);
     }
     tile_body<R, L, C, NT, MODE, FK, D, CPLX, FS>(v, kt, lds, tl, p, t, tw);
@@ -784,6 +816,16 @@ hipError_t launch_shape(const PassDesc& p, int kind, hipStream_t s, const GroupA
         using I0 = std::integral_constant<int, 0>;
         using T_ = std::true_type;
         using F_ = std::false_type;
+        if (p.table_full) {
+            // full complex table (convection kernel)
+            if (!p.table_complex) return hipErrorInvalidValue;
+            if (p.fs_L1) {
+                if (p.d != 2 || p.post_tw != 2) return hipErrorInvalidValue;
+                return by_kind(I2{}, T_{}, std::integral_constant<int, 2 | 16>{});
+            }
+            if (p.d == 3) return by_kind(I3{}, T_{}, std::integral_constant<int, 16>{});
+            return by_kind(I2{}, T_{}, std::integral_constant<int, 16>{});
+        }
         if (p.fs_L1) {
             // four-step step B (2D only)
             if (p.d != 2 || p.post_tw != 2) return hipErrorInvalidValue;

@@ -89,6 +89,11 @@ template <typename R>
 __device__ __forceinline__ cplx<R> table_value(const PassDesc& p, int e, int col, long long o) {
     const int L = axis_len(p);
     const int k = axis_index(p, e, o);
+    if (p.table_full) {
+        // every spectral index stored: flat = k L^(d-1) + column
+        const long long plane = p.d == 3 ? (long long)L * L : (long long)L;
+        return reinterpret_cast<const cplx<R>*>(p.table)[(long long)k * plane + col];
+    }
     const int N1 = p.tabN + 1;
     const int f1 = min(k, L - k);
     long long flat;

@@ -125,7 +125,15 @@ void fill_greens_params(const vg_plan* p, GreensParams& g) {
     g.L = p->L;
     g.ds = 2.0 * M_PI / p->P;
     const double L = p->L, k = p->k;
-    const bool helm = p->kernel == VG_HELMHOLTZ || p->kernel == VG_LAPLACE_HELMHOLTZ;
+    const bool conv = p->kernel == VG_CONVECTION;
+    const bool helm = p->kernel == VG_HELMHOLTZ || p->kernel == VG_LAPLACE_HELMHOLTZ || conv;
+    if (conv) {
+        // evaluated as the Helmholtz transform with k = |h| at |s - h|
+        g.kernel = VG_HELMHOLTZ;
+        g.full = 1;
+        g.M = p->P * p->N;
+        for (int i = 0; i < 3; ++i) g.h[i] = p->h[i];
+    }
     if (helm && p->d == 3) {
         // power series of (1/s) int_0^L sin(sr) e^{ikr} dr in x^2 = (sL)^2:
         // a_j = L^2 (-1)^j/(2j+1)! sum_p (ikL)^p / (p! (2j+2+p))
@@ -185,8 +193,131 @@ vg_status upload(DevBuf& b, const std::vector<double>& h, hipStream_t s) {
 
 }  // namespace
 
+// Convection kernel (Tables 1-2, last row): G_h(s) = G_{|h|}(|s - h|) has no
+// per-axis symmetry, so T lives on all offsets |n_j| <= N-1 (2N-1 per axis)
+// and Khat on the full (2N)^d box.  Each axis is a complex DFT contraction,
+// done as a cosine and a sine contraction combined as a + sign i b.
+vg_status precompute_full(vg_plan* p, hipStream_t s, bool keep_T) {
+    const int d = p->d, N = p->N;
+    const long long M = (long long)p->P * N, NT = 2LL * N - 1, L = 2LL * N;
+    auto dft = [&](long long rows_out, long long cols_in, bool lattice, bool sine) {
+        // lattice: [nn][m], angle 2 pi m_s n / M, scale 1/M (T);
+        // otherwise [k][nn], angle 2 pi k n / (2N), scale 1/(2N) (Khat)
+        std::vector<double> c((size_t)(rows_out * cols_in));
+        for (long long r = 0; r < rows_out; ++r)
+            for (long long q = 0; q < cols_in; ++q) {
+                long long t, period;
+                double scale;
+                if (lattice) {
+                    const long long ms = q < M / 2 ? q : q - M;
+                    t = ms * (r - (N - 1));
+                    period = M;
+                    scale = 1.0 / (double)M;
+                } else {
+                    t = r * (q - (N - 1));
+                    period = L;
+                    scale = 1.0 / (double)L;
+                }
+                t %= period;
+                if (t < 0) t += period;
+                const long double v = sine ? twopi_frac_sin(t, period) : twopi_frac_cos(t, period);
+                c[(size_t)(r * cols_in + q)] = (double)(v * (long double)scale);
+            }
+        return c;
+    };
+    DevBuf dCl, dSl, dCk, dSk;
+    vg_status st = upload(dCl, dft(NT, M, true, false), s);
+    if (st == VG_OK) st = upload(dSl, dft(NT, M, true, true), s);
+    if (st == VG_OK) st = upload(dCk, dft(L, NT, false, false), s);
+    if (st == VG_OK) st = upload(dSk, dft(L, NT, false, true), s);
+    if (st != VG_OK) return st;
+    GreensParams g;
+    fill_greens_params(p, g);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    if (he != hipSuccess) return from_hip(he, "hipEventCreate");
+    (void)hipEventRecord(e0, s);
+    auto chk = [&](hipError_t e, const char* what) -> vg_status { return from_hip(e, what); };
+    // one complex contraction of the middle index of X[O][Min][I]: Y = X C + sign i X S
+    DevBuf tmp;
+    auto contract = [&](const DevBuf& in, DevBuf& out, const DevBuf& C, const DevBuf& S, long long O, int Min, int Nout,
+                        long long I, int sign) -> vg_status {
+        const size_t n = (size_t)(O * Nout * I);
+        hipError_t e = out.alloc(n * 16);
+        if (e == hipSuccess && !tmp.p) e = tmp.alloc(n * 16);
+        if (e != hipSuccess) return chk(e, "precompute buffer");
+        if ((e = launch_cos_contract(in.as<c64>(), out.as<c64>(), C.as<double>(), O, Min, Nout, I, s)) != hipSuccess)
+            return chk(e, "contraction");
+        if ((e = launch_cos_contract(in.as<c64>(), tmp.as<c64>(), S.as<double>(), O, Min, Nout, I, s)) != hipSuccess)
+            return chk(e, "contraction");
+        if ((e = launch_combine(out.as<c64>(), tmp.as<c64>(), out.as<c64>(), (long long)n, sign, s)) != hipSuccess)
+            return chk(e, "combine");
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return chk(e, "precompute");
+        (void)hipFree(tmp.p);
+        tmp.p = nullptr;
+        return VG_OK;
+    };
+    DevBuf X1, X2, T, K1, K2, K;
+    {
+        long long rows = 1;
+        for (int i = 0; i < d - 1; ++i) rows *= M;
+        const size_t n = (size_t)(rows * NT);
+        if ((he = X1.alloc(n * 16)) != hipSuccess || (he = tmp.alloc(n * 16)) != hipSuccess) return chk(he, "precompute buffer");
+        if ((he = launch_greens_contract_full(g, (int)NT, dCl.as<double>(), X1.as<c64>(), s)) != hipSuccess) return chk(he, "kernel spectrum");
+        if ((he = launch_greens_contract_full(g, (int)NT, dSl.as<double>(), tmp.as<c64>(), s)) != hipSuccess) return chk(he, "kernel spectrum");
+        if ((he = launch_combine(X1.as<c64>(), tmp.as<c64>(), X1.as<c64>(), (long long)n, +1, s)) != hipSuccess) return chk(he, "combine");
+        if ((he = hipStreamSynchronize(s)) != hipSuccess) return chk(he, "precompute");
+        (void)hipFree(tmp.p);
+        tmp.p = nullptr;
+    }
+    DevBuf* Tb;
+    if (d == 3) {
+        if ((st = contract(X1, X2, dCl, dSl, M, (int)M, (int)NT, NT, +1)) != VG_OK) return st;
+        (void)hipFree(X1.p);
+        X1.p = nullptr;
+        if ((st = contract(X2, T, dCl, dSl, 1, (int)M, (int)NT, NT * NT, +1)) != VG_OK) return st;
+        (void)hipFree(X2.p);
+        X2.p = nullptr;
+        if ((st = contract(T, K1, dCk, dSk, 1, (int)NT, (int)L, NT * NT, -1)) != VG_OK) return st;
+        if ((st = contract(K1, K2, dCk, dSk, L, (int)NT, (int)L, NT, -1)) != VG_OK) return st;
+        (void)hipFree(K1.p);
+        K1.p = nullptr;
+        if ((st = contract(K2, K, dCk, dSk, L * L, (int)NT, (int)L, 1, -1)) != VG_OK) return st;
+        Tb = &T;
+    } else {
+        if ((st = contract(X1, T, dCl, dSl, 1, (int)M, (int)NT, NT, +1)) != VG_OK) return st;
+        (void)hipFree(X1.p);
+        X1.p = nullptr;
+        if ((st = contract(T, K1, dCk, dSk, 1, (int)NT, (int)L, NT, -1)) != VG_OK) return st;
+        if ((st = contract(K1, K, dCk, dSk, L, (int)NT, (int)L, 1, -1)) != VG_OK) return st;
+        Tb = &T;
+    }
+    long long nK = 1;
+    for (int i = 0; i < d; ++i) nK *= L;
+    p->table_complex = 1;
+    const size_t esz = p->fp64 ? 16 : 8;
+    p->table_bytes = (size_t)nK * esz;
+    if ((he = dev_malloc(&p->table, p->table_bytes)) != hipSuccess) return chk(he, "kernel table");
+    if ((he = launch_round_table(K.as<c64>(), p->table, nK, p->fp64 ? 0 : 1, 1, s)) != hipSuccess)
+        return chk(he, "table rounding");
+    (void)hipEventRecord(e1, s);
+    if ((he = hipStreamSynchronize(s)) != hipSuccess) return chk(he, "precompute");
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    p->precompute_ms = ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (keep_T) {
+        p->T_dev = Tb->p;
+        Tb->p = nullptr;
+    }
+    return VG_OK;
+}
+
 // FP64 precompute: kernel spectrum -> T (octant) -> Khat (octant) -> table.
 vg_status precompute(vg_plan* p, hipStream_t s, bool keep_T) {
+    if (p->kernel == VG_CONVECTION) return precompute_full(p, s, keep_T);
     const int d = p->d, N = p->N;
     const long long M = (long long)p->P * N;
     const int M2 = (int)(M / 2 + 1);
@@ -653,6 +784,7 @@ vg_status build_programs(vg_plan* p, hipStream_t stream) {
                 st.desc.tw_big = p->twiddles[st.desc.L_big];
             }
             st.desc.xcd_map = p->cfg.xcd_map;
+            st.desc.table_full = p->kernel == VG_CONVECTION ? 1 : 0;
             bool spec = false;
             st.desc.C = choose_C(p, st, &spec);
             st.desc.specialised = spec ? 1 : 0;

@@ -59,6 +59,7 @@ struct vg_plan {
     double tune_ms = 0.0;     // wall time of the autotuner
     int tune_candidates = 0;  // configurations timed
     double k = 0.0, L = 0.0;
+    double h[3] = {0.0, 0.0, 0.0};  // convection vector (VG_CONVECTION)
     int device = 0;
     bool fp64 = false;
     std::vector<int> radices;     // Stockham radix plan of length 2N

@@ -237,7 +237,21 @@ __global__ void __launch_bounds__(256) contract_kernel(const c64* __restrict__ X
             const int m = m0 + mm;
             c64 v = mk(0.0, 0.0);
             if (row < rows && m < K) {
-                if (GEN) {
+                if (GEN && g.full) {
+                    // row -> leading lattice indices (FFT order), shifted by h:
+                    // |s_m - h| with s_m = ds * signed(m); the last axis is m
+                    const int hm = g.M / 2;
+                    double ds2 = g.ds * (double)(m < hm ? m : m - g.M) - g.h[g.d - 1];
+                    double sq = ds2 * ds2;
+                    long long rem = row;
+                    for (int ax = g.d - 2; ax >= 0; --ax) {
+                        const long long mi = rem % K;
+                        rem /= K;
+                        const double sv = g.ds * (double)(mi < hm ? mi : mi - g.M) - g.h[ax];
+                        sq += sv * sv;
+                    }
+                    v = g_eval(sqrt(sq), g);
+                } else if (GEN) {
                     // row -> leading octant indices
                     double sq = (double)m * m;
                     long long rem = row;
@@ -306,6 +320,14 @@ __global__ void __launch_bounds__(256) contract_kernel(const c64* __restrict__ X
     }
 }
 
+__global__ void combine_kernel(const c64* __restrict__ a, const c64* __restrict__ b, c64* __restrict__ out, long long n,
+                               double sign) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const c64 x = a[i], y = b[i];
+    out[i] = mk(x.x - sign * y.y, x.y + sign * y.x);
+}
+
 __global__ void round_table_kernel(const c64* __restrict__ in, void* __restrict__ out, long long n, int to_fp32,
                                    int complex_out) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -336,6 +358,20 @@ hipError_t launch_greens_contract(const GreensParams& g, int M2, int n_out, cons
     for (int ax = 0; ax < g.d - 1; ++ax) rows *= M2;
     const dim3 grid((unsigned)((rows + TR - 1) / TR), (unsigned)((n_out + TN - 1) / TN));
     hipLaunchKernelGGL(contract_kernel<true>, grid, dim3(256), 0, s, nullptr, out, cmat, rows, M2, n_out, 1LL, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_greens_contract_full(const GreensParams& g, int n_out, const double* cmat, c64* out, hipStream_t s) {
+    long long rows = 1;
+    for (int ax = 0; ax < g.d - 1; ++ax) rows *= g.M;
+    const dim3 grid((unsigned)((rows + TR - 1) / TR), (unsigned)((n_out + TN - 1) / TN));
+    hipLaunchKernelGGL(contract_kernel<true>, grid, dim3(256), 0, s, nullptr, out, cmat, rows, g.M, n_out, 1LL, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const c64* a, const c64* b, c64* out, long long n, int sign, hipStream_t s) {
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(combine_kernel, dim3(blocks), dim3(256), 0, s, a, b, out, n, (double)sign);
     return hipGetLastError();
 }
 

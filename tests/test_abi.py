@@ -46,7 +46,13 @@ BAD = [
     (dict(d=3, N=8, kernel=1, k=0.0), 1),     # Helmholtz needs k > 0
     (dict(d=3, N=8, kernel=1, k=float("nan")), 1),
     (dict(d=3, N=8, kernel=7), 1),       # unknown kernel
-    (dict(d=3, N=8, kernel=4), 1),
+    (dict(d=3, N=8, kernel=5), 1),
+    (dict(d=3, N=8, kernel=4), 1),       # convection needs h with |h| > 0
+    (dict(d=2, N=8, kernel=4, h=(0.0, 0.0)), 1),
+    (dict(d=3, N=8, kernel=4, h=(1.0, float("inf"), 0.0)), 1),
+    (dict(d=3, N=8, kernel=4, h=(float("nan"), 1.0, 0.0)), 1),
+    (dict(d=3, N=320, kernel=4, h=(1.0, 0.0, 0.0)), 2),   # 3D convection limited to N <= 256
+    (dict(d=2, N=16384, kernel=4, h=(1.0, 0.0)), 2),      # (2N)^2 complex64 table above 4 GiB
     (dict(d=2, N=8, kernel=3, k=0.0), 1),     # Delta(Delta + k^2) needs k > 0
     (dict(d=2, N=8, kernel=3, k=-2.0), 1),
     (dict(d=3, N=8, L=1.5), 1),          # L below sqrt(3)
@@ -61,7 +67,9 @@ BAD = [
 @pytest.mark.parametrize("args,code", BAD)
 def test_invalid_arguments_rejected_without_device(vgmod, args, code):
     lib = ctypes.CDLL(vgmod.LIBRARY_PATH)
-    opts = vgmod._Opts(args.get("precision", 0), args.get("L", 0.0), args.get("P", 0), 0, 0, None)
+    hv = list(args.get("h", ())) + [0.0] * (3 - len(args.get("h", ())))
+    opts = vgmod._Opts(args.get("precision", 0), args.get("L", 0.0), args.get("P", 0), 0, 0, None,
+                       (ctypes.c_double * 3)(*hv))
     h = ctypes.c_void_p(123)
     st = lib.vg_plan_create_ex(args["d"], args["N"], args.get("kernel", 0), ctypes.c_double(args.get("k", 0.0)),
                                ctypes.byref(opts), ctypes.byref(h))
