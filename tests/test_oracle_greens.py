@@ -151,3 +151,30 @@ def test_laplace_helmholtz_is_difference_and_vanishes_as_k_to_0():
         assert np.array_equal(g.kernel_transform(d, "laplace_helmholtz", s, 9.0), diff)
     small = g.kernel_transform(3, "laplace_helmholtz", s, 1e-4)
     assert np.max(np.abs(small)) < 1e-3
+
+
+def test_helmholtz2d_near_shell_against_high_precision():
+    """The stable evaluation next to s = k, where Table 2's quotient is 0/0,
+    against the printed form evaluated with 40 significant digits (mpmath),
+    for wavenumbers from kL < 1 to kL = 1500: pointwise relative error below
+    2e-13 on both sides of the Taylor window's edge (1.3e-13 at k = 1000 just
+    outside it, where the printed form has lost about eps k)."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 40
+    L = 1.5
+    for k in (0.5, 2.0, 37.0, 200.0, 1000.0):
+        ds = np.array([-3.0, -1.0001, -0.9999, -0.3, -1e-2, -1e-4, 0.0, 1e-4, 1e-2, 0.3, 0.9999, 1.0001, 3.0])
+        s = k + ds
+        s = s[s > 0]
+        got = g.g_helmholtz2d(s, k, L)
+        x = L * mp.mpf(k)
+        H0, H1 = mp.hankel1(0, x), mp.hankel1(1, x)
+        for sv, gv in zip(s, got):
+            sm = mp.mpf(float(sv))
+            if sm == mp.mpf(k):
+                exact = 0.25j * mp.pi * L * L * (mp.besselj(0, x) * H0 + mp.besselj(1, x) * H1)
+            else:
+                num = 1 + 0.5j * mp.pi * L * (sm * mp.besselj(1, L * sm) * H0 - k * mp.besselj(0, L * sm) * H1)
+                exact = num / ((sm - k) * (sm + k))
+            exact = complex(exact)
+            assert abs(gv - exact) <= 2e-13 * abs(exact), (k, sv - k)
