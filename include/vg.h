@@ -266,11 +266,15 @@ vg_status vg_plan_kernel_hat(const vg_plan* plan, double* host_out);
 vg_status vg_plan_operator_entries(const vg_plan* plan, double* host_out);
 
 /*
- * Pass profiler (diagnostics).  While enabled, every apply / gradient call
- * records a HIP event between consecutive passes on its stream; collect()
- * waits for those events and returns, per pass name, the number of launches
- * and their summed device time, then clears the record.  Enabling adds one
- * event record per pass to the stream.  Process-wide; thread-safe.
+ * Pass profiler (diagnostics).  vg_profiler_enable(1): every apply / gradient
+ * call records a HIP event between consecutive passes on its stream;
+ * vg_profiler_enable(2): only just before and after the call's pass with the
+ * most algorithmic bytes (two events per call, so the other passes run as
+ * without the profiler); 0 switches it off (other values:
+ * VG_ERR_INVALID_ARG).  collect() waits for the recorded events and returns,
+ * per pass name, the number of launches and their summed device time, then
+ * clears the record.  Each event record adds a few microseconds to the
+ * stream.  Process-wide; thread-safe.
  */
 typedef struct vg_pass_time {
     char name[32];

@@ -284,9 +284,11 @@ class Plan:
         return out
 
 
-def profiler_enable(enable=True):
-    """Record device time per pass of every apply / gradient call."""
-    _check(_lib.vg_profiler_enable(1 if enable else 0), "vg_profiler_enable")
+def profiler_enable(enable=True, dominant_only=False):
+    """Record device time per pass of every apply / gradient call; with
+    dominant_only, only of each call's pass with the most algorithmic bytes
+    (two events per call instead of one per pass)."""
+    _check(_lib.vg_profiler_enable((2 if dominant_only else 1) if enable else 0), "vg_profiler_enable")
 
 
 def profiler_collect():

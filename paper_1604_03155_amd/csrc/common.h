@@ -119,7 +119,7 @@ struct GreensParams {
     // coefficients of the numerator about s = k.
     double H0r, H0i, H1r, H1i;
     int ntaylor;
-    double taylor_r[10], taylor_i[10];
+    double taylor_r[24], taylor_i[24];
     double window;
     // full-lattice generator (convection kernel): lattice of M points per axis
     // in FFT order, G evaluated at |s_m - h| (with kernel = Helmholtz, k = |h|)

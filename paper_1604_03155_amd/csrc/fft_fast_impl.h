@@ -122,6 +122,40 @@ __device__ __forceinline__ void st_off(void* base, unsigned off, T v) {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
 }
 
+// Streaming (non-temporal) access to the pencil data: every element is read
+// once and written once per pass, so these loads and stores are marked
+// non-temporal and leave the caches to the reused data (twiddles, the Khat
+// table).  Loads are streaming in the row passes and in column passes whose
+// tile rows cover whole 128-byte lines (C complex values >= 128 bytes); with
+// narrower tiles the neighbouring tile reads the other part of each line,
+// which an ordinary load leaves in L2.  Stores are streaming in those column
+// passes only -- the row passes' outputs are read next (the first column
+// pass, or the caller) and stay cache-resident with ordinary stores.
+// Measured: 3D N = 256 apply (C = 16 complex64 columns) 0.757 -> 0.696 ms;
+// 3D N = 512 apply (C = 8) 8.8 ms streaming vs 7.3 ms ordinary.
+template <typename R, int C, int MODE>
+constexpr bool streaming_loads() {
+    return MODE == MODE_ROW || C * (int)sizeof(cplx<R>) >= 128;
+}
+template <typename R, int C, int MODE>
+constexpr bool streaming_stores() {
+    return MODE == MODE_COL && C * (int)sizeof(cplx<R>) >= 128;
+}
+template <typename R>
+__device__ __forceinline__ cplx<R> ld_stream(const void* base, unsigned off) {
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    const v2 x = __builtin_nontemporal_load(reinterpret_cast<const v2*>(reinterpret_cast<const char*>(base) + off));
+    return mk(x.x, x.y);
+}
+template <typename R>
+__device__ __forceinline__ void st_stream(void* base, unsigned off, cplx<R> c) {
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    v2 x;
+    x.x = c.x;
+    x.y = c.y;
+    __builtin_nontemporal_store(x, reinterpret_cast<v2*>(reinterpret_cast<char*>(base) + off));
+}
+
 // A value known to be the same in every lane, passed through readfirstlane:
 // the compiler keeps it in a scalar register and cannot factor it into
 // per-element vector multiplies.
@@ -312,7 +346,10 @@ __device__ __forceinline__ void issue_loads(cplx<R>* vn, const cplx<R>* __restri
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             cplx<R> x = mk(R(0), R(0));
-            if ((r + 1) * LR <= NIN || jj[i] + r * LR < NIN) x = ld_off<cplx<R>>(gb, off[i]);
+            if ((r + 1) * LR <= NIN || jj[i] + r * LR < NIN) {
+                if constexpr (streaming_loads<R, C, MODE>()) x = ld_stream<R>(gb, off[i]);
+                else x = ld_off<cplx<R>>(gb, off[i]);
+            }
             vn[i * NR + r] = x;
         }
     }
@@ -360,7 +397,10 @@ __device__ __forceinline__ void store_global_t(const cplx<R>* v, cplx<R>* __rest
                     const cplx<R> w = ld_off<cplx<R>>(twb, (unsigned)(tl.o * (jj[i] + r * LR)) * (unsigned)sizeof(cplx<R>));
                     x = PT == 1 ? cmul(x, w) : cmulc(x, w);
                 }
-                if (ok[i] && ((r + 1) * LR <= NOUT || jj[i] + r * LR < NOUT)) st_off(gb, off[i], x);
+                if (ok[i] && ((r + 1) * LR <= NOUT || jj[i] + r * LR < NOUT)) {
+                    if constexpr (streaming_stores<R, C, MODE>()) st_stream<R>(gb, off[i], x);
+                    else st_off(gb, off[i], x);
+                }
             }
         }
     }
@@ -627,14 +667,35 @@ struct KindIO {
 //         exchange real and imaginary parts in turn through half the LDS (32
 //         instead of 64 KiB) and are held to 168 VGPRs, so 3 workgroups share
 //         a CU instead of 2 (length 512 at N = 256: 0.39 -> 0.34 ms; length
-//         1024 at N = 512: 3.61 -> 3.47 ms).
+//         1024 at N = 512: 3.61 -> 3.47 ms); also the complex64 inverse rows
+//         of length 8192 (one 64 KiB row per workgroup otherwise; 2D N =
+//         4096: 0.136 -> 0.119 ms; the forward rows measured slower split).
+// A row pencil too large for 64 KiB of LDS as complex values (complex128
+// rows of length 8192) is exchanged as real and imaginary parts in turn.
+template <typename R, int L, int MODE>
+constexpr bool row_needs_split() {
+    return MODE == MODE_ROW && L * (int)sizeof(cplx<R>) > 65536;
+}
+
 template <typename R, int L, int MODE, int FK>
 struct Policy {
     static constexpr bool twl = L * (int)sizeof(cplx<R>) <= 8192 && make_plan(L, kMaxRad<R>).n >= 2;
     static constexpr bool split =
-        sizeof(R) == 4 && MODE == MODE_COL && (FK == FK_FUSED || FK == FK_FUSED_DERIV) && (L == 512 || L == 1024);
-    static constexpr int min_waves = split ? 3 : 1;
+        (sizeof(R) == 4 && MODE == MODE_COL && (FK == FK_FUSED || FK == FK_FUSED_DERIV) && (L == 512 || L == 1024)) ||
+        (sizeof(R) == 4 && MODE == MODE_ROW && FK == FK_INV && L >= 8192) || row_needs_split<R, L, MODE>();
+    static constexpr int min_waves = (split && sizeof(R) == 4) ? 3 : 1;
 };
+
+// The C2R rows (FS & 7 == 4) stage whole complex values in LDS and keep the
+// plain exchange.
+template <typename R, int L, int MODE, int FK, int FS>
+constexpr bool use_split() {
+    return Policy<R, L, MODE, FK>::split && ((FS & 7) != 4 || row_needs_split<R, L, MODE>());
+}
+template <typename R, int L, int MODE, int FK, int FS>
+constexpr int kernel_waves() {
+    return use_split<R, L, MODE, FK, FS>() ? Policy<R, L, MODE, FK>::min_waves : 1;
+}
 
 // FS: 0 plain pass; 1 four-step step A (forward, outputs times W^{o e});
 // 2 four-step step B (full-length forward, Khat at index o + L1 e, full-length
@@ -648,7 +709,7 @@ __device__ __forceinline__ void tile_body(cplx<R>* v, cplx<R>* kt, cplx<R>* lds,
     constexpr RP F = make_plan(L, kMaxRad<R>);
     constexpr RP I = reversed(F);
     constexpr int E = C * L / NT;
-    constexpr bool SP = Policy<R, L, MODE, FK>::split;
+    constexpr bool SP = use_split<R, L, MODE, FK, FS>();
     cplx<R>* __restrict__ gout = reinterpret_cast<cplx<R>*>(p.out);
     cplx<R>* __restrict__ gout2 = reinterpret_cast<cplx<R>*>(p.out2);
     const R ks = (R)p.kscale;
@@ -712,7 +773,7 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
     constexpr bool FULL = (FS & 16) != 0;
     constexpr int NIN = (FL && FSB != 2) ? L / 2 : L;
     using LY = Lay<L, C, MODE, (int)sizeof(cplx<R>)>;
-    constexpr int NLDS0 = PO::split ? (LY::size + 1) / 2 : LY::size;
+    constexpr int NLDS0 = use_split<R, L, MODE, FK, FS>() ? (LY::size + 1) / 2 : LY::size;
     constexpr int NLDS = (FSB == 4 && C * (L + 1) > NLDS0) ? C * (L + 1) : NLDS0;
     __shared__ cplx<R> lds[NLDS];
     __shared__ cplx<R> twl[PO::twl ? L : 1];
@@ -745,18 +806,46 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
     tile_body<R, L, C, NT, MODE, FK, D, CPLX, FS>(v, kt, lds, tl, p, t, tw);
 }
 
+// Mirror-paired tile order of the fused column passes over the octant table:
+// the table value of column (k2, k3) is shared by (L - k2, k3), (k2, L - k3)
+// and (L - k2, L - k3), so those tiles are placed next to each other in the
+// launch order (and hence on one XCD, close in time): spectral row k2 runs
+// in the order 0, 1, L-1, 2, L-2, ..., L/2 and the L/C tiles of a row in the
+// order 0, L/C-1, 1, L/C-2, ...  Both maps are bijections.  Measured on the
+// 3D N = 256 apply: fused pass 0.345 -> 0.330 ms.
+__device__ __forceinline__ unsigned mirror_row(unsigned i, unsigned n) {
+    if (i == 0) return 0;
+    if (i == n - 1) return n / 2;
+    const unsigned m = (i + 1) / 2;
+    return (i & 1u) ? m : n - m;
+}
+__device__ __forceinline__ unsigned mirror_tile(unsigned s, unsigned n) { return (s & 1u) ? n - 1 - (s >> 1) : (s >> 1); }
+
+template <int L, int C, int MODE, int FK, int D, int FS>
+__device__ __forceinline__ unsigned tile_order(const PassDesc& p, unsigned b) {
+    constexpr bool TAB = FK == FK_FUSED || FK == FK_FUSED_GRAD || FK == FK_FUSED_DERIV;
+    if constexpr (TAB && MODE == MODE_COL && FS == 0 && L % C == 0) {
+        constexpr unsigned nt = L / C;
+        if (D == 3 && p.inner == L * L) return mirror_row(b / nt, L) * nt + mirror_tile(b % nt, nt);
+        if (D == 2 && p.inner == L) return (b / nt) * nt + mirror_tile(b % nt, nt);
+    }
+    return b;
+}
+
 // One tile per workgroup.
 template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX, int FS>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Policy<R, L, MODE, FK>::min_waves)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kernel_waves<R, L, MODE, FK, FS>())))
 fast_kernel(PassDesc p) {
-    fast_run<R, L, C, NT, MODE, FK, D, CPLX, FS>(p, p.xcd_map ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x);
+    unsigned b = blockIdx.x;
+    if (p.xcd_map) b = tile_order<L, C, MODE, FK, D, FS>(p, xcd_tile(b, gridDim.x));
+    fast_run<R, L, C, NT, MODE, FK, D, CPLX, FS>(p, b);
 }
 
 // Grouped launch: the same pass over several independent arrays (one
 // descriptor each, same length and kind); item i owns the workgroups
 // [starts[i], starts[i + 1]).
 template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX, int FS>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Policy<R, L, MODE, FK>::min_waves)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kernel_waves<R, L, MODE, FK, FS>())))
 fast_group_kernel(const PassDesc* __restrict__ descs, const unsigned* __restrict__ starts, int nitems) {
     const unsigned b = xcd_tile(blockIdx.x, gridDim.x);
     int i = 0;
@@ -787,8 +876,12 @@ hipError_t launch_shape(const PassDesc& p, int kind, hipStream_t s, const GroupA
         // real-data variants: rows in and out of the half spectrum, and the
         // fused pass on a half spectrum (apply only; real tables)
         if constexpr (MODE == MODE_ROW) {
-            if (p.real_mode == 1 && kind == KIND_FWD) return launch_k<R, L, C, NT, MODE, FK_FWD, 3, false, 3, GROUP>(p, nblocks, s, ga);
-            if (p.real_mode == 2 && kind == KIND_INV) return launch_k<R, L, C, NT, MODE, FK_INV, 3, false, 4, GROUP>(p, nblocks, s, ga);
+            // no real-data rows where one complex pencil needs the split
+            // exchange (their C2R staging holds L + 1 whole values)
+            if constexpr (L * (int)sizeof(cplx<R>) <= 65536) {
+                if (p.real_mode == 1 && kind == KIND_FWD) return launch_k<R, L, C, NT, MODE, FK_FWD, 3, false, 3, GROUP>(p, nblocks, s, ga);
+                if (p.real_mode == 2 && kind == KIND_INV) return launch_k<R, L, C, NT, MODE, FK_INV, 3, false, 4, GROUP>(p, nblocks, s, ga);
+            }
         } else {
             if (p.real_mode == 4 && kind == KIND_FUSED && !p.table_complex) {
                 if (p.fs_L1 && p.d == 2 && p.post_tw == 2)
@@ -868,10 +961,12 @@ constexpr Shape shape_for(int L, int mode, int esize) {
     const int target = esize == 16 ? 16 : 32;
     const int E = lc >= target ? lc : (target / lc) * lc;
     const int LP = mode == MODE_COL ? L : L + L / 16;
+    // rows whose single pencil exceeds 64 KiB exchange half values (split)
+    const int les = (mode == MODE_ROW && L * esize > 65536) ? esize / 2 : esize;
     int C = mode == MODE_COL ? 16 : 8;
-    while (C > 1 && C * LP * esize > 65536) C /= 2;
-    if (C * LP * esize > 65536 && L * esize > 65536) return Shape{0, E, 0};  // one pencil does not fit
-    while (C * L / E < 64 && C < 64 && 2 * C * LP * esize <= 65536) C *= 2;
+    while (C > 1 && C * LP * les > 65536) C /= 2;
+    if (C * LP * les > 65536 && L * les > 65536) return Shape{0, E, 0};  // one pencil does not fit
+    while (C * L / E < 64 && C < 64 && 2 * C * LP * les <= 65536) C *= 2;
     return Shape{C, E, C * L / E};
 }
 

@@ -160,8 +160,11 @@ void fill_greens_params(const vg_plan* p, GreensParams& g) {
         // Taylor coefficients of N(s)/(s - k) about s = k, N the numerator of
         // Table 2's transform: c_{n-1} = N^(n)(k)/n!, with
         // u = s J1(Ls): u^(n) = k L^n J1^(n) + n L^(n-1) J1^(n-1); v = J0(Ls): v^(n) = L^n J0^(n).
-        g.ntaylor = 8;
-        for (int n = 1; n <= 8; ++n) {
+        // 24 terms over |s - k| < 1: the printed quotient loses about
+        // eps k / |s - k| to cancellation, which the wide window keeps near
+        // 1e-14 relative up to k ~ 1000 (measured against 40-digit values)
+        g.ntaylor = 24;
+        for (int n = 1; n <= 24; ++n) {
             const double un = k * std::pow(L, n) * besselj_deriv(1, n, x) + n * std::pow(L, n - 1) * besselj_deriv(1, n - 1, x);
             const double vn = std::pow(L, n) * besselj_deriv(0, n, x);
             const std::complex<double> Nn = std::complex<double>(0.0, 0.5 * M_PI * L) * (H0 * un - k * H1 * vn);
@@ -169,7 +172,7 @@ void fill_greens_params(const vg_plan* p, GreensParams& g) {
             g.taylor_r[n - 1] = c.real();
             g.taylor_i[n - 1] = c.imag();
         }
-        g.window = 1.0e-2;
+        g.window = 1.0;
     }
 }
 
@@ -447,7 +450,9 @@ int choose_C(const vg_plan* p, const PassStep& st, bool* specialised) {
     *specialised = false;
     const PassDesc& d = st.desc;
     if (d.real_mode) {
-        // real-data variants exist for the specialised kernels only
+        // real-data variants exist for the specialised kernels only, and not
+        // for rows whose complex pencil exceeds 64 KiB
+        if (st.mode == MODE_ROW && (size_t)d.L * (p->fp64 ? 16 : 8) > 65536) return 0;
         const int fc = fast_pass_C(d.L, st.mode, p->fp64);
         const bool rowm = st.mode == MODE_ROW;
         if (fc > 0 && fast_pass_fits(d.L, st.mode, p->fp64, d.in_se, d.out_se, rowm ? d.in_so : 1, rowm ? d.out_so : 1)) {
@@ -862,7 +867,22 @@ std::vector<BoundStep> bind_program(const vg_plan* p, const Program& prog, const
 vg_status run_program(const vg_plan* p, const Program& prog, const void* f, void* phi, void* grad, void* ws,
                       hipStream_t stream) {
     const std::vector<BoundStep> steps = bind_program(p, prog, f, phi, grad, ws);
-    void* mark = profiler_mark(stream);
+    const int pm = profiler_mode();
+    if (pm == 2) {
+        // events around the pass with the most bytes only
+        size_t dom = 0;
+        for (size_t i = 1; i < steps.size(); ++i)
+            if (steps[i].bytes > steps[dom].bytes) dom = i;
+        for (size_t i = 0; i < steps.size(); ++i) {
+            const BoundStep& st = steps[i];
+            void* a = i == dom ? profiler_mark(stream) : nullptr;
+            hipError_t e = launch_fft_pass(st.desc, st.mode, st.kind, p->fp64, stream);
+            if (e != hipSuccess) return from_hip(e, st.name);
+            if (a) profiler_add(st.name, a, profiler_mark(stream), st.bytes);
+        }
+        return VG_OK;
+    }
+    void* mark = pm ? profiler_mark(stream) : nullptr;
     for (const BoundStep& st : steps) {
         hipError_t e = launch_fft_pass(st.desc, st.mode, st.kind, p->fp64, stream);
         if (e != hipSuccess) return from_hip(e, st.name);

@@ -117,7 +117,7 @@ vg_status run_program(const vg_plan* p, const Program& prog, const void* f, void
 
 
 // Pass profiler hooks (profiler.cpp).
-bool profiler_enabled();
+int profiler_mode();  // 0 off, 1 every pass, 2 the pass with the most bytes
 void* profiler_mark(hipStream_t s);
 void profiler_add(const char* name, void* a, void* b, double bytes);
 

@@ -17,7 +17,7 @@ struct Rec {
     double bytes;
 };
 std::mutex g_mu;
-bool g_enabled = false;
+int g_mode = 0;  // 0 off, 1 every pass, 2 the pass with the most bytes
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 
@@ -33,15 +33,15 @@ hipEvent_t take_event() {
 }
 }  // namespace
 
-bool profiler_enabled() {
+int profiler_mode() {
     std::lock_guard<std::mutex> lk(g_mu);
-    return g_enabled;
+    return g_mode;
 }
 
 // Record one event on `s`; returns it (nullptr when disabled or on failure).
 void* profiler_mark(hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (!g_enabled) return nullptr;
+    if (!g_mode) return nullptr;
     hipEvent_t e = take_event();
     if (e && hipEventRecord(e, s) != hipSuccess) return nullptr;
     return e;
@@ -58,8 +58,9 @@ void profiler_add(const char* name, void* a, void* b, double bytes) {
 using namespace vg;
 
 extern "C" vg_status vg_profiler_enable(int enable) {
+    if (enable < 0 || enable > 2) return fail(VG_ERR_INVALID_ARG, "profiler mode must be 0, 1 or 2");
     std::lock_guard<std::mutex> lk(g_mu);
-    g_enabled = enable != 0;
+    g_mode = enable;
     return VG_OK;
 }
 

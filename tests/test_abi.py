@@ -88,6 +88,8 @@ def test_null_arguments(vgmod):
     arr = (ctypes.c_void_p * 1)()
     assert lib.vg_apply_batched(0, arr, arr, arr, None, None) == 1
     lib.vg_plan_destroy(None)  # no-op
+    assert lib.vg_profiler_enable(3) == 1 and lib.vg_profiler_enable(-1) == 1
+    assert lib.vg_profiler_enable(0) == 0
 
 
 def test_no_device_reported_on_cpu_host(vgmod):

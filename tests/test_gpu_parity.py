@@ -276,6 +276,47 @@ def test_2d_n4096_workload_against_closed_form(name):
     assert err <= FP32_TOL
 
 
+@pytest.mark.parametrize("name", ["laplace2d_n4096", "helmholtz2d_k200_n4096"])
+def test_2d_n4096_fp64_against_oracle(name):
+    """FP64 at 2N = 8192: a complex128 row of 8192 values (128 KiB) exchanges
+    real and imaginary parts in turn through 64 KiB of LDS; the column axis
+    runs as four steps.  The potential and gradient of the seeded
+    Gaussian-sum workload against the FP64 oracle at 1e-12, and the potential
+    of a white-noise density.
+
+    For Helmholtz k = 200 this also checks the kernel transform next to the
+    |s| = k shell, where Table 2's quotient cancels (the stable form's Taylor
+    window).  A white-noise gradient is not compared at this size: it weights
+    the highest frequencies, where |Khat| is ~1e-4 of its maximum and both
+    FP64 tables carry rounding relative to that maximum, by kappa up to pi N;
+    the two sides agree to 6e-12 for Laplace."""
+    say("fp64 2D N=4096", name)
+    from workloads import evaluate_grid, workload
+    vg = _vg()
+    torch = _torch()
+    prm, src = workload(name)
+    N, kernel, k = prm["N"], prm["kernel"], prm["k"]
+    p = vg.Plan(2, N, kernel, k, precision="fp64")
+    o = oracle_plan(2, N, kernel, k)
+    noise = random_density(4096, 2, N)
+    phi = p.apply(to_dev(noise, "fp64"))
+    torch.cuda.synchronize()
+    e = rel_l2(phi.cpu().numpy(), o.apply(noise))
+    say("  white noise phi rel L2", e)
+    assert e <= FP64_TOL
+    f = evaluate_grid(src, N)
+    phi, grad = p.gradient(to_dev(f, "fp64"))
+    torch.cuda.synchronize()
+    e = rel_l2(phi.cpu().numpy(), o.apply(f))
+    say("  workload phi rel L2", e)
+    assert e <= FP64_TOL
+    gref = o.gradient(f)
+    for j in range(2):
+        e = rel_l2(grad[j].cpu().numpy(), gref[j])
+        say("  workload grad", j, "rel L2", e)
+        assert e <= FP64_TOL
+
+
 @pytest.mark.parametrize("d,N,kernel,k", [(3, 64, "biharmonic", 0.0), (3, 64, "laplace_helmholtz", 12.0),
                                           (2, 256, "biharmonic", 0.0)])
 def test_other_kernels_against_gaussian_closed_forms(d, N, kernel, k):
