@@ -126,9 +126,10 @@ __device__ __forceinline__ void st_off(void* base, unsigned off, T v) {
 // once and written once per pass, so these loads and stores are marked
 // non-temporal and leave the caches to the reused data (twiddles, the Khat
 // table).  Loads are streaming in the row passes and in column passes whose
-// tile rows cover whole 128-byte lines (C complex values >= 128 bytes); with
-// narrower tiles the neighbouring tile reads the other part of each line,
-// which an ordinary load leaves in L2.  Stores are streaming in those column
+// tile rows cover whole 128-byte lines (C complex values >= 128 bytes, and
+// pitches that keep them line-aligned: PassDesc::stream, set by the host);
+// otherwise the neighbouring tile reads the other part of each line, which
+// an ordinary load leaves in L2.  Stores are streaming in those column
 // passes only -- the row passes' outputs are read next (the first column
 // pass, or the caller) and stay cache-resident with ordinary stores.
 // Measured: 3D N = 256 apply (C = 16 complex64 columns) 0.757 -> 0.696 ms;
@@ -263,6 +264,7 @@ struct FTile {
     int nvalid;
     int col0;
     int o;                  // outer index (column tiles)
+    int stream;             // streaming access allowed (PassDesc::stream)
 };
 
 // XCD-aware order for one-tile-per-workgroup launches: dispatch slot b runs
@@ -274,6 +276,7 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb) {
 template <int C, int MODE>
 __device__ __forceinline__ FTile fast_tile(const PassDesc& p, unsigned b) {
     FTile t;
+    t.stream = p.stream;
     if constexpr (MODE == MODE_COL) {
         const int ntile = (p.inner + C - 1) / C;
         const long long o = b / ntile;
@@ -340,19 +343,23 @@ __device__ __forceinline__ void issue_loads(cplx<R>* vn, const cplx<R>* __restri
         off[i] = (unsigned)((long long)q * tl.iq + (long long)j * se) * (unsigned)sizeof(cplx<R>);
         jj[i] = j;
     }
+    auto body = [&](auto stream) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const cplx<R>* gb = g + tl.in0 + (long long)(r * LR) * se;
+        for (int r = 0; r < NR; ++r) {
+            const cplx<R>* gb = g + tl.in0 + (long long)(r * LR) * se;
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            cplx<R> x = mk(R(0), R(0));
-            if ((r + 1) * LR <= NIN || jj[i] + r * LR < NIN) {
-                if constexpr (streaming_loads<R, C, MODE>()) x = ld_stream<R>(gb, off[i]);
-                else x = ld_off<cplx<R>>(gb, off[i]);
+            for (int i = 0; i < NB; ++i) {
+                cplx<R> x = mk(R(0), R(0));
+                if ((r + 1) * LR <= NIN || jj[i] + r * LR < NIN) {
+                    if constexpr (decltype(stream)::value) x = ld_stream<R>(gb, off[i]);
+                    else x = ld_off<cplx<R>>(gb, off[i]);
+                }
+                vn[i * NR + r] = x;
             }
-            vn[i * NR + r] = x;
         }
-    }
+    };
+    if (streaming_loads<R, C, MODE>() && tl.stream) body(std::true_type{});
+    else body(std::false_type{});
 }
 
 template <typename R, int L, int C, int NT, RP P, int NIN>
@@ -386,24 +393,29 @@ __device__ __forceinline__ void store_global_t(const cplx<R>* v, cplx<R>* __rest
         off[i] = (unsigned)((long long)q * tl.oq + (long long)j * se) * (unsigned)sizeof(cplx<R>);
         jj[i] = j;
     }
+    auto body = [&](auto stream) {
 #pragma unroll
-    for (int r = 0; r < RAD; ++r) {
-        if (r * LR < NOUT) {
-            cplx<R>* gb = g + tl.out0 + (long long)(r * LR) * se;
+        for (int r = 0; r < RAD; ++r) {
+            if (r * LR < NOUT) {
+                cplx<R>* gb = g + tl.out0 + (long long)(r * LR) * se;
 #pragma unroll
-            for (int i = 0; i < E / RAD; ++i) {
-                cplx<R> x = v[i * RAD + r];
-                if constexpr (PT != 0) {
-                    const cplx<R> w = ld_off<cplx<R>>(twb, (unsigned)(tl.o * (jj[i] + r * LR)) * (unsigned)sizeof(cplx<R>));
-                    x = PT == 1 ? cmul(x, w) : cmulc(x, w);
-                }
-                if (ok[i] && ((r + 1) * LR <= NOUT || jj[i] + r * LR < NOUT)) {
-                    if constexpr (streaming_stores<R, C, MODE>()) st_stream<R>(gb, off[i], x);
-                    else st_off(gb, off[i], x);
+                for (int i = 0; i < E / RAD; ++i) {
+                    cplx<R> x = v[i * RAD + r];
+                    if constexpr (PT != 0) {
+                        const cplx<R> w =
+                            ld_off<cplx<R>>(twb, (unsigned)(tl.o * (jj[i] + r * LR)) * (unsigned)sizeof(cplx<R>));
+                        x = PT == 1 ? cmul(x, w) : cmulc(x, w);
+                    }
+                    if (ok[i] && ((r + 1) * LR <= NOUT || jj[i] + r * LR < NOUT)) {
+                        if constexpr (decltype(stream)::value) st_stream<R>(gb, off[i], x);
+                        else st_off(gb, off[i], x);
+                    }
                 }
             }
         }
-    }
+    };
+    if (streaming_stores<R, C, MODE>() && tl.stream) body(std::true_type{});
+    else body(std::false_type{});
 }
 
 template <typename R, int L, int C, int NT, int MODE, RP P, int NOUT, int PT = 0>

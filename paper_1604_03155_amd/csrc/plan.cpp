@@ -789,6 +789,17 @@ vg_status build_programs(vg_plan* p, hipStream_t stream) {
                 st.desc.tw_big = p->twiddles[st.desc.L_big];
             }
             st.desc.xcd_map = p->cfg.xcd_map;
+            {
+                // streaming access only where column tile rows stay on whole
+                // 128-byte lines (measured: the half-spectrum columns of the
+                // real path, pitch N + 1, lose 25% with it)
+                const long long es = p->fp64 ? 16 : 8;
+                auto al = [&](long long x) { return (x * es) % 128 == 0; };
+                st.desc.stream = (st.mode == MODE_ROW || (al(st.desc.in_se) && al(st.desc.out_se) &&
+                                                          al(st.desc.in_so) && al(st.desc.out_so)))
+                                     ? 1
+                                     : 0;
+            }
             st.desc.table_full = p->kernel == VG_CONVECTION ? 1 : 0;
             bool spec = false;
             st.desc.C = choose_C(p, st, &spec);
