@@ -970,7 +970,13 @@ constexpr Shape shape_for(int L, int mode, int esize) {
     const RP p = make_plan(L, esize == 8 ? 32 : 16);
     int lc = 1;
     for (int i = 0; i < p.n; ++i) lc = lc / gcd_i(lc, p.r[i]) * p.r[i];
-    const int target = esize == 16 ? 16 : 32;
+    // elements per thread: at least 32 complex64 (16 complex128) values, for
+    // butterfly-level parallelism in a thread, except complex64 lengths 96 to
+    // 256 (the 3D N = 48..128 grids), where 16 gives twice the waves and
+    // measured faster (3D N = 128 apply 0.115 -> 0.101 ms, N = 64 0.034 ->
+    // 0.029 ms; the 64-density batch 2.48 -> 2.39 ms); shorter lengths (the
+    // four-step pieces of 2D N = 1024) measured slower with 16
+    const int target = esize == 16 ? 16 : ((L >= 96 && L <= 256) ? 16 : 32);
     const int E = lc >= target ? lc : (target / lc) * lc;
     const int LP = mode == MODE_COL ? L : L + L / 16;
     // rows whose single pencil exceeds 64 KiB exchange half values (split)
