@@ -132,8 +132,11 @@ typedef struct vg_plan_info {
  * Runs the FP64 precompute of Sections 2 and 4 on the current device and
  * synchronises before returning.
  * Errors: VG_ERR_INVALID_ARG (bad arguments; *out untouched),
- * VG_ERR_UNSUPPORTED_SIZE (2N has a prime factor above 7), VG_ERR_NO_DEVICE,
- * VG_ERR_OUT_OF_MEMORY, VG_ERR_DEVICE.  On error *out is set to NULL.
+ * VG_ERR_UNSUPPORTED_SIZE (2N has a prime factor above 7, or a pass whose
+ * pencil fits no kernel: a 2D row of 2N values must fit one workgroup's LDS,
+ * which allows 2N up to 8192 for the lengths with specialised kernels and
+ * up to 10240 otherwise), VG_ERR_NO_DEVICE, VG_ERR_OUT_OF_MEMORY,
+ * VG_ERR_DEVICE.  On error *out is set to NULL.
  */
 vg_status vg_plan_create(int d, int N, vg_kernel kernel, double k, vg_plan** out);
 vg_status vg_plan_create_ex(int d, int N, vg_kernel kernel, double k,

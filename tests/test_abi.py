@@ -99,3 +99,16 @@ def test_no_device_reported_on_cpu_host(vgmod):
     h = ctypes.c_void_p()
     st = vgmod._lib.vg_plan_create(3, 8, 0, 0.0, ctypes.byref(h))
     assert st == 4  # VG_ERR_NO_DEVICE
+
+
+def test_header_is_plain_c_and_cpp():
+    """include/vg.h is the boundary for C callers too: it must compile as C99
+    and as C++17 on its own."""
+    import shutil
+    import subprocess
+    for cc, args in (("gcc", ["-x", "c", "-std=c99"]), ("g++", ["-x", "c++", "-std=c++17"])):
+        if shutil.which(cc) is None:
+            pytest.skip(f"{cc} not installed")
+        r = subprocess.run([cc, "-fsyntax-only", "-Wall", "-Wextra", "-Werror", *args, HEADER],
+                           capture_output=True, text=True)
+        assert r.returncode == 0, (cc, r.stderr)
