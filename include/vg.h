@@ -173,6 +173,9 @@ vg_status vg_apply(const vg_plan* plan, const void* f, void* phi,
  * workspace: at least vg_gradient_workspace_size(plan) bytes, or NULL.
  * The derivative multiplies the (2N)^d spectrum by i pi m_j (m_j the signed
  * frequency, zero at the Nyquist index m_j = N).
+ * Errors: VG_ERR_INVALID_ARG (NULL plan/f/grad), VG_ERR_UNSUPPORTED_SIZE
+ * (2D plans with 2N above 8192 whose two-output gradient rows do not fit in
+ * LDS; their applies still run), VG_ERR_DEVICE (launch).
  */
 vg_status vg_gradient(const vg_plan* plan, const void* f, void* phi, void* grad,
                       void* workspace, void* stream);

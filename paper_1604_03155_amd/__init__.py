@@ -32,6 +32,11 @@ _KERNELS = {"laplace": LAPLACE, "helmholtz": HELMHOLTZ, "biharmonic": BIHARMONIC
 if not os.path.exists(LIBRARY_PATH):
     raise ImportError(f"{LIBRARY_PATH} is missing: build it with `python paper_1604_03155_amd/build.py`")
 
+# torch is loaded first so that the library binds to the HIP runtime torch
+# already carries: loading the library first would bring in a second HIP
+# runtime (the system one), and the two then disagree about the devices.
+import torch as _torch_mod  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIBRARY_PATH)
 
 

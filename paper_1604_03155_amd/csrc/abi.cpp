@@ -207,6 +207,8 @@ vg_status vg_gradient(const vg_plan* p, const void* f, void* phi, void* grad, vo
     return guarded([&]() -> vg_status {
         if (!p) return fail(VG_ERR_INVALID_ARG, "plan is NULL");
         if (!f || !grad) return fail(VG_ERR_INVALID_ARG, "f and grad must be device pointers");
+        if (p->grad_prog.steps.empty())
+            return fail(VG_ERR_UNSUPPORTED_SIZE, "no gradient kernels for this size (a gradient pass exceeds the LDS)");
         void* ws = nullptr;
         vg_status st = get_ws(p, p->grad_prog.ws_bytes, workspace, &ws);
         if (st != VG_OK) return st;

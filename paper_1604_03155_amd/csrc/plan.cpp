@@ -808,11 +808,13 @@ vg_status build_programs(vg_plan* p, hipStream_t stream) {
             bool spec = false;
             st.desc.C = choose_C(p, st, &spec);
             st.desc.specialised = spec ? 1 : 0;
-            if (st.desc.C == 0 && pr == &Rr) {
-                // no real-data variant for this length: real applies unsupported
-                Rr.steps.clear();
-                Rr.ws_offsets.clear();
-                Rr.ws_bytes = 0;
+            if (st.desc.C == 0 && (pr == &Rr || pr == &G)) {
+                // no real-data variant for this length, or a gradient pass
+                // (two-output kinds hold more LDS) that fits no kernel: real
+                // applies or gradients are unsupported, applies are not
+                pr->steps.clear();
+                pr->ws_offsets.clear();
+                pr->ws_bytes = 0;
                 break;
             }
             if (st.desc.C == 0) return fail(VG_ERR_UNSUPPORTED_SIZE, std::string("pass ") + st.name + ": pencil does not fit in LDS");

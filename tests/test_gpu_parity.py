@@ -366,3 +366,25 @@ def test_truncation_radius_and_oversampling_options(d, N, kernel, k, L, P):
     phi = p.apply(to_dev(f, "fp64"))
     torch.cuda.synchronize()
     assert rel_l2(phi.cpu().numpy(), o.apply(f)) <= FP64_TOL
+
+
+def test_size_limits_of_2d_rows():
+    """2N = 10240 (no specialised row kernel): the apply runs on the generic
+    kernel with a whole row in LDS and matches the oracle; the two-output
+    gradient rows do not fit, so vg_gradient reports VG_ERR_UNSUPPORTED_SIZE.
+    2N = 16384: no row kernel at all, plan creation fails cleanly."""
+    say("2D size limits")
+    vg = _vg()
+    torch = _torch()
+    with pytest.raises(vg.VGError, match="UNSUPPORTED_SIZE"):
+        vg.Plan(2, 8192, "laplace")
+    N = 5120
+    p = vg.Plan(2, N, "laplace", precision="fp32")
+    f = random_density(5120, 2, N)
+    phi = p.apply(to_dev(f, "fp32"))
+    torch.cuda.synchronize()
+    e = rel_l2(phi.cpu().numpy(), oracle_plan(2, N, "laplace", 0.0).apply(f))
+    say("  N=5120 apply rel L2", e)
+    assert e <= FP32_TOL
+    with pytest.raises(vg.VGError, match="UNSUPPORTED_SIZE"):
+        p.gradient(to_dev(f, "fp32"))
