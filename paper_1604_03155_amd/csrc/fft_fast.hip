@@ -26,6 +26,20 @@ int fast_C_4096(int mode, bool fp64);
 hipError_t launch_fast_4096(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
 int fast_C_8192(int mode, bool fp64);
 hipError_t launch_fast_8192(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
+int fast_C_100(int mode, bool fp64);
+hipError_t launch_fast_100(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
+int fast_C_200(int mode, bool fp64);
+hipError_t launch_fast_200(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
+int fast_C_400(int mode, bool fp64);
+hipError_t launch_fast_400(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
+int fast_C_500(int mode, bool fp64);
+hipError_t launch_fast_500(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
+int fast_C_300(int mode, bool fp64);
+hipError_t launch_fast_300(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
+int fast_C_3200(int mode, bool fp64);
+hipError_t launch_fast_3200(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
+int fast_C_6400(int mode, bool fp64);
+hipError_t launch_fast_6400(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
 
 // (declarations of the per-length offset checks)
 bool fast_fits_32(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
@@ -39,6 +53,13 @@ bool fast_fits_1024(int mode, bool fp64, long long ise, long long ose, long long
 bool fast_fits_2048(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
 bool fast_fits_4096(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
 bool fast_fits_8192(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
+bool fast_fits_100(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
+bool fast_fits_200(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
+bool fast_fits_400(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
+bool fast_fits_500(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
+bool fast_fits_300(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
+bool fast_fits_3200(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
+bool fast_fits_6400(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
 
 // Pencils per workgroup the specialised kernel uses for (L, mode, precision),
 // or 0 when no specialisation exists (the generic kernel is used).
@@ -55,6 +76,13 @@ int fast_pass_C(int L, int mode, bool fp64) {
         case 2048: return fast_C_2048(mode, fp64);
         case 4096: return fast_C_4096(mode, fp64);
         case 8192: return fast_C_8192(mode, fp64);
+        case 100: return fast_C_100(mode, fp64);
+        case 200: return fast_C_200(mode, fp64);
+        case 400: return fast_C_400(mode, fp64);
+        case 500: return fast_C_500(mode, fp64);
+        case 300: return fast_C_300(mode, fp64);
+        case 3200: return fast_C_3200(mode, fp64);
+        case 6400: return fast_C_6400(mode, fp64);
         default: return 0;
     }
 }
@@ -73,6 +101,13 @@ bool fast_pass_fits(int L, int mode, bool fp64, long long ise, long long ose, lo
         case 2048: return fast_fits_2048(mode, fp64, ise, ose, iiq, oiq);
         case 4096: return fast_fits_4096(mode, fp64, ise, ose, iiq, oiq);
         case 8192: return fast_fits_8192(mode, fp64, ise, ose, iiq, oiq);
+        case 100: return fast_fits_100(mode, fp64, ise, ose, iiq, oiq);
+        case 200: return fast_fits_200(mode, fp64, ise, ose, iiq, oiq);
+        case 400: return fast_fits_400(mode, fp64, ise, ose, iiq, oiq);
+        case 500: return fast_fits_500(mode, fp64, ise, ose, iiq, oiq);
+        case 300: return fast_fits_300(mode, fp64, ise, ose, iiq, oiq);
+        case 3200: return fast_fits_3200(mode, fp64, ise, ose, iiq, oiq);
+        case 6400: return fast_fits_6400(mode, fp64, ise, ose, iiq, oiq);
         default: return false;
     }
 }
@@ -90,6 +125,13 @@ hipError_t launch_fast_pass(const PassDesc& p, int mode, int kind, bool fp64, hi
         case 2048: return launch_fast_2048(p, mode, kind, fp64, s);
         case 4096: return launch_fast_4096(p, mode, kind, fp64, s);
         case 8192: return launch_fast_8192(p, mode, kind, fp64, s);
+        case 100: return launch_fast_100(p, mode, kind, fp64, s);
+        case 200: return launch_fast_200(p, mode, kind, fp64, s);
+        case 400: return launch_fast_400(p, mode, kind, fp64, s);
+        case 500: return launch_fast_500(p, mode, kind, fp64, s);
+        case 300: return launch_fast_300(p, mode, kind, fp64, s);
+        case 3200: return launch_fast_3200(p, mode, kind, fp64, s);
+        case 6400: return launch_fast_6400(p, mode, kind, fp64, s);
         default: return hipErrorInvalidValue;
     }
 }

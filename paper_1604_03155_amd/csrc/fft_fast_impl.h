@@ -985,6 +985,7 @@ constexpr Shape shape_for(int L, int mode, int esize) {
     while (C > 1 && C * LP * les > 65536) C /= 2;
     if (C * LP * les > 65536 && L * les > 65536) return Shape{0, E, 0};  // one pencil does not fit
     while (C * L / E < 64 && C < 64 && 2 * C * LP * les <= 65536) C *= 2;
+    if (C * L / E < 64) return Shape{0, E, 0};  // under one wave: left to the generic kernel
     return Shape{C, E, C * L / E};
 }
 

@@ -388,3 +388,51 @@ def test_size_limits_of_2d_rows():
     assert e <= FP32_TOL
     with pytest.raises(vg.VGError, match="UNSUPPORTED_SIZE"):
         p.gradient(to_dev(f, "fp32"))
+
+
+@pytest.mark.parametrize("N,k,precisions", [(50, 20.0, ("fp32", "fp64")), (100, 40.0, ("fp32", "fp64")),
+                                            (150, 60.0, ("fp32", "fp64")), (200, 80.0, ("fp32",)),
+                                            (250, 100.0, ("fp32",))])
+def test_paper_3d_grid_sizes_mixed_radix(N, k, precisions):
+    """The 3D grid sizes of the paper's scattering runs (N = 50 to 250, so 2N
+    = 100 to 500 = 2^a 3^b 5^c): length-specialised kernels with radix-3 and
+    radix-5 stages.  Potential (and, up to N = 150, gradient) against the
+    oracle."""
+    say("paper 3D size", N, k)
+    vg = _vg()
+    torch = _torch()
+    f = random_density(900 + N, 3, N)
+    o = oracle_plan(3, N, "helmholtz", k)
+    ref = o.apply(f)
+    for precision in precisions:
+        p = vg.Plan(3, N, "helmholtz", k, precision=precision)
+        x = to_dev(f, precision)
+        phi, grad = p.gradient(x)
+        torch.cuda.synchronize()
+        tol = FP64_TOL if precision == "fp64" else FP32_TOL
+        e = rel_l2(phi.cpu().numpy(), ref)
+        say("  ", precision, "phi", e)
+        assert e <= tol
+        if N <= 150:
+            gref = o.gradient(f)
+            for j in range(3):
+                assert rel_l2(grad[j].cpu().numpy(), gref[j]) <= tol, j
+        del p, x, phi, grad
+        torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("N,k", [(1600, 100.0), (3200, 200.0)])
+def test_paper_2d_grid_sizes_mixed_radix(N, k):
+    """2D grid sizes of the paper's scattering runs (2N = 3200 and 6400 = 2^a
+    5^2): specialised rows of length 2N with radix-5 stages, four-step columns
+    with a length-100 / 200 first step."""
+    say("paper 2D size", N, k)
+    vg = _vg()
+    torch = _torch()
+    f = random_density(700 + N, 2, N)
+    p = vg.Plan(2, N, "helmholtz", k, precision="fp32")
+    phi = p.apply(to_dev(f, "fp32"))
+    torch.cuda.synchronize()
+    e = rel_l2(phi.cpu().numpy(), oracle_plan(2, N, "helmholtz", k).apply(f))
+    say("  fp32 phi", e, "four-step L1", p.info["four_step_L1"])
+    assert e <= FP32_TOL
