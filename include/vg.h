@@ -134,9 +134,10 @@ typedef struct vg_plan_info {
  * Errors: VG_ERR_INVALID_ARG (bad arguments; *out untouched),
  * VG_ERR_UNSUPPORTED_SIZE (2N has a prime factor above 7, or a pass whose
  * pencil fits no kernel: a 2D row of 2N values must fit one workgroup's LDS,
- * which allows 2N up to 8192 for the lengths with specialised kernels and
- * up to 10240 otherwise), VG_ERR_NO_DEVICE, VG_ERR_OUT_OF_MEMORY,
- * VG_ERR_DEVICE.  On error *out is set to NULL.
+ * which allows 2N up to 12800 for the lengths with specialised row kernels
+ * (complex64; 8192 for complex128) and up to 10240 otherwise),
+ * VG_ERR_NO_DEVICE, VG_ERR_OUT_OF_MEMORY, VG_ERR_DEVICE.  On error *out is
+ * set to NULL.
  */
 vg_status vg_plan_create(int d, int N, vg_kernel kernel, double k, vg_plan** out);
 vg_status vg_plan_create_ex(int d, int N, vg_kernel kernel, double k,
@@ -174,8 +175,9 @@ vg_status vg_apply(const vg_plan* plan, const void* f, void* phi,
  * The derivative multiplies the (2N)^d spectrum by i pi m_j (m_j the signed
  * frequency, zero at the Nyquist index m_j = N).
  * Errors: VG_ERR_INVALID_ARG (NULL plan/f/grad), VG_ERR_UNSUPPORTED_SIZE
- * (2D plans with 2N above 8192 whose two-output gradient rows do not fit in
- * LDS; their applies still run), VG_ERR_DEVICE (launch).
+ * (2D plans whose two-output gradient rows do not fit in LDS, e.g. 2N =
+ * 10240 on the generic kernel; their applies still run), VG_ERR_DEVICE
+ * (launch).
  */
 vg_status vg_gradient(const vg_plan* plan, const void* f, void* phi, void* grad,
                       void* workspace, void* stream);

@@ -40,6 +40,8 @@ int fast_C_3200(int mode, bool fp64);
 hipError_t launch_fast_3200(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
 int fast_C_6400(int mode, bool fp64);
 hipError_t launch_fast_6400(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
+int fast_C_12800(int mode, bool fp64);
+hipError_t launch_fast_12800(const PassDesc& p, int mode, int kind, bool fp64, hipStream_t s);
 
 // (declarations of the per-length offset checks)
 bool fast_fits_32(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
@@ -60,6 +62,7 @@ bool fast_fits_500(int mode, bool fp64, long long ise, long long ose, long long 
 bool fast_fits_300(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
 bool fast_fits_3200(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
 bool fast_fits_6400(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
+bool fast_fits_12800(int mode, bool fp64, long long ise, long long ose, long long iiq, long long oiq);
 
 // Pencils per workgroup the specialised kernel uses for (L, mode, precision),
 // or 0 when no specialisation exists (the generic kernel is used).
@@ -83,6 +86,7 @@ int fast_pass_C(int L, int mode, bool fp64) {
         case 300: return fast_C_300(mode, fp64);
         case 3200: return fast_C_3200(mode, fp64);
         case 6400: return fast_C_6400(mode, fp64);
+        case 12800: return fast_C_12800(mode, fp64);
         default: return 0;
     }
 }
@@ -108,6 +112,7 @@ bool fast_pass_fits(int L, int mode, bool fp64, long long ise, long long ose, lo
         case 300: return fast_fits_300(mode, fp64, ise, ose, iiq, oiq);
         case 3200: return fast_fits_3200(mode, fp64, ise, ose, iiq, oiq);
         case 6400: return fast_fits_6400(mode, fp64, ise, ose, iiq, oiq);
+        case 12800: return fast_fits_12800(mode, fp64, ise, ose, iiq, oiq);
         default: return false;
     }
 }
@@ -132,6 +137,7 @@ hipError_t launch_fast_pass(const PassDesc& p, int mode, int kind, bool fp64, hi
         case 300: return launch_fast_300(p, mode, kind, fp64, s);
         case 3200: return launch_fast_3200(p, mode, kind, fp64, s);
         case 6400: return launch_fast_6400(p, mode, kind, fp64, s);
+        case 12800: return launch_fast_12800(p, mode, kind, fp64, s);
         default: return hipErrorInvalidValue;
     }
 }

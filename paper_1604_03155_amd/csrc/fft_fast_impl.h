@@ -695,7 +695,8 @@ struct Policy {
     static constexpr bool split =
         (sizeof(R) == 4 && MODE == MODE_COL && (FK == FK_FUSED || FK == FK_FUSED_DERIV) && (L == 512 || L == 1024)) ||
         (sizeof(R) == 4 && MODE == MODE_ROW && FK == FK_INV && L >= 8192) || row_needs_split<R, L, MODE>();
-    static constexpr int min_waves = (split && sizeof(R) == 4) ? 3 : 1;
+    // the two-output kinds (two spectra per thread) keep the default budget
+    static constexpr int min_waves = (split && sizeof(R) == 4 && FK != FK_INV_GRAD && FK != FK_FUSED_GRAD) ? 3 : 1;
 };
 
 // The C2R rows (FS & 7 == 4) stage whole complex values in LDS and keep the

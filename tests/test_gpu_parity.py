@@ -421,11 +421,12 @@ def test_paper_3d_grid_sizes_mixed_radix(N, k, precisions):
         torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("N,k", [(1600, 100.0), (3200, 200.0)])
+@pytest.mark.parametrize("N,k", [(1600, 100.0), (3200, 200.0), (6400, 200.0)])
 def test_paper_2d_grid_sizes_mixed_radix(N, k):
-    """2D grid sizes of the paper's scattering runs (2N = 3200 and 6400 = 2^a
-    5^2): specialised rows of length 2N with radix-5 stages, four-step columns
-    with a length-100 / 200 first step."""
+    """2D grid sizes of the paper's scattering runs (2N = 3200, 6400 and 12800
+    = 2^a 5^2): specialised rows of length 2N with radix-5 stages (at 12800 a
+    100 KiB row exchanged as real and imaginary parts in turn), four-step
+    columns with a length-100 / 200 / 400 first step."""
     say("paper 2D size", N, k)
     vg = _vg()
     torch = _torch()
