@@ -437,3 +437,25 @@ def test_paper_2d_grid_sizes_mixed_radix(N, k):
     e = rel_l2(phi.cpu().numpy(), oracle_plan(2, N, "helmholtz", k).apply(f))
     say("  fp32 phi", e, "four-step L1", p.info["four_step_L1"])
     assert e <= FP32_TOL
+
+
+@pytest.mark.parametrize("N", [50, 100, 150, 200, 250, 320])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_2d_mixed_radix_lengths_rows_and_columns(N, precision):
+    """2D grids whose 2N (100 ... 500, 640) takes the mixed-radix specialised
+    kernels on both axes (640 the generic one): potential and gradient of the
+    Helmholtz and Laplace kernels against the oracle."""
+    say("2D mixed radix", N, precision)
+    vg = _vg()
+    torch = _torch()
+    f = random_density(1300 + N, 2, N)
+    tol = FP64_TOL if precision == "fp64" else FP32_TOL
+    for kernel, k in (("helmholtz", 0.2 * N), ("laplace", 0.0)):
+        p = vg.Plan(2, N, kernel, k, precision=precision)
+        phi, grad = p.gradient(to_dev(f, precision))
+        torch.cuda.synchronize()
+        o = oracle_plan(2, N, kernel, k)
+        assert rel_l2(phi.cpu().numpy(), o.apply(f)) <= tol, kernel
+        gref = o.gradient(f)
+        for j in range(2):
+            assert rel_l2(grad[j].cpu().numpy(), gref[j]) <= tol, (kernel, j)
