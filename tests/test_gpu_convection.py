@@ -6,9 +6,9 @@ The kernel is not symmetric per axis, so the plan holds T on every offset
 table.  Bars as for the other kernels: FP64 plans within 1e-12 of the FP64
 oracle (tables relative to their largest entry, applies and gradients in
 relative L2), FP32 plans within 1e-5.  Cases cover the specialised lengths
-(2N in {32, 64, 96, 128, 512, 1024}), generic lengths (2N = 20, 24, 60), the
-2D four-step column pass (N = 1024), gradients, the generic-kernel switch and
-grouped batches.
+(2N in {32, 64, 96, 100, 128, 300, 512, 1024}), generic lengths (2N = 20,
+24, 60), the 2D four-step column pass (N = 1024), gradients, the
+generic-kernel switch and grouped batches.
 """
 import sys
 
@@ -82,7 +82,7 @@ def test_convection_table_fp32_rounded_once():
 APPLY_CASES = [(3, 8, (3.0, -2.0, 1.5)), (3, 10, (1.0, 4.0, -2.0)), (3, 12, (0.0, 6.0, 0.0)),
                (3, 16, (7.0, 7.0, -7.0)), (3, 32, (-12.0, 5.0, 9.0)), (3, 48, (20.0, -10.0, 3.0)),
                (2, 10, (4.0, -1.0)), (2, 30, (15.0, 22.0)), (2, 64, (-40.0, 10.0)), (2, 256, (70.0, -80.0)),
-               (2, 512, (0.5, 0.25))]
+               (2, 512, (0.5, 0.25)), (3, 50, (8.0, -3.0, 5.0)), (2, 150, (25.0, 40.0))]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
