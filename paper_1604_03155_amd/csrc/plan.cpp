@@ -176,6 +176,15 @@ void fill_greens_params(const vg_plan* p, GreensParams& g) {
     }
 }
 
+// The precompute's timing events, released on every return path.
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
 struct DevBuf {
     void* p = nullptr;
     ~DevBuf() {
@@ -236,10 +245,11 @@ vg_status precompute_full(vg_plan* p, hipStream_t s, bool keep_T) {
     if (st != VG_OK) return st;
     GreensParams g;
     fill_greens_params(p, g);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t he = hipEventCreate(&e0);
-    if (he == hipSuccess) he = hipEventCreate(&e1);
+    EventPair ev;
+    hipError_t he = hipEventCreate(&ev.a);
+    if (he == hipSuccess) he = hipEventCreate(&ev.b);
     if (he != hipSuccess) return from_hip(he, "hipEventCreate");
+    hipEvent_t e0 = ev.a, e1 = ev.b;
     (void)hipEventRecord(e0, s);
     auto chk = [&](hipError_t e, const char* what) -> vg_status { return from_hip(e, what); };
     // one complex contraction of the middle index of X[O][Min][I]: Y = X C + sign i X S
@@ -309,8 +319,6 @@ vg_status precompute_full(vg_plan* p, hipStream_t s, bool keep_T) {
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
     p->precompute_ms = ms;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (keep_T) {
         p->T_dev = Tb->p;
         Tb->p = nullptr;
@@ -341,10 +349,11 @@ vg_status precompute(vg_plan* p, hipStream_t s, bool keep_T) {
     GreensParams g;
     fill_greens_params(p, g);
 
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t he = hipEventCreate(&e0);
-    if (he == hipSuccess) he = hipEventCreate(&e1);
+    EventPair ev;
+    hipError_t he = hipEventCreate(&ev.a);
+    if (he == hipSuccess) he = hipEventCreate(&ev.b);
     if (he != hipSuccess) return from_hip(he, "hipEventCreate");
+    hipEvent_t e0 = ev.a, e1 = ev.b;
     (void)hipEventRecord(e0, s);
 
     const long long Nl = N, M2l = M2, N1 = N + 1;
@@ -395,8 +404,6 @@ vg_status precompute(vg_plan* p, hipStream_t s, bool keep_T) {
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
     p->precompute_ms = ms;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (keep_T) {
         p->T_dev = T.p;  // ownership moves to the plan
         T.p = nullptr;
