@@ -23,7 +23,10 @@ def rel_l2(a, b):
 CASES = [(3, 32, "laplace", "fp32"), (3, 64, "biharmonic", "fp32"), (3, 128, "laplace", "fp32"),
          (3, 32, "laplace", "fp64"), (3, 64, "biharmonic", "fp64"), (2, 64, "laplace", "fp32"),
          (2, 256, "biharmonic", "fp32"), (2, 512, "laplace", "fp64"), (2, 1024, "laplace", "fp32"),
-         (2, 1024, "biharmonic", "fp64")]
+         (2, 1024, "biharmonic", "fp64"),
+         # mixed-radix lengths (rows of N, columns of 2N with radix-3 / radix-5 stages)
+         (3, 100, "laplace", "fp32"), (3, 200, "laplace", "fp32"), (3, 100, "biharmonic", "fp64"),
+         (2, 200, "laplace", "fp32"), (2, 3200, "laplace", "fp32")]
 
 
 @pytest.mark.parametrize("d,N,kernel,precision", CASES)
