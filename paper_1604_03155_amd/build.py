@@ -37,12 +37,15 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
+# the slowest translation units first, so the parallel build ends sooner
+# (the radix-3/5 lengths with 60 values per thread take the longest)
+_SLOW_FIRST = ("fft_fast_300.hip", "fft_fast_200.hip", "fft_group_200.hip")
+
+
 def sources():
-    out = []
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".cpp")):
-            out.append(os.path.join(CSRC, name))
-    return out
+    names = [n for n in os.listdir(CSRC) if n.endswith((".hip", ".cpp"))]
+    names.sort(key=lambda n: (n not in _SLOW_FIRST, not n.startswith("fft_"), n))
+    return [os.path.join(CSRC, n) for n in names]
 
 
 def compile_one(src):

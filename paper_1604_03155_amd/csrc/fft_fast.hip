@@ -151,8 +151,15 @@ hipError_t launch_fast_group_192(const PassDesc& proto, const GroupArgs& g, int 
 hipError_t launch_fast_group_256(const PassDesc& proto, const GroupArgs& g, int mode, int kind, bool fp64, hipStream_t s);
 hipError_t launch_fast_group_512(const PassDesc& proto, const GroupArgs& g, int mode, int kind, bool fp64, hipStream_t s);
 hipError_t launch_fast_group_1024(const PassDesc& proto, const GroupArgs& g, int mode, int kind, bool fp64, hipStream_t s);
+hipError_t launch_fast_group_100(const PassDesc& proto, const GroupArgs& g, int mode, int kind, bool fp64, hipStream_t s);
+hipError_t launch_fast_group_200(const PassDesc& proto, const GroupArgs& g, int mode, int kind, bool fp64, hipStream_t s);
+hipError_t launch_fast_group_400(const PassDesc& proto, const GroupArgs& g, int mode, int kind, bool fp64, hipStream_t s);
+hipError_t launch_fast_group_500(const PassDesc& proto, const GroupArgs& g, int mode, int kind, bool fp64, hipStream_t s);
 
-bool fast_group_supported(int L) { return L == 32 || L == 64 || L == 96 || L == 128 || L == 192 || L == 256 || L == 512 || L == 1024; }
+bool fast_group_supported(int L) {
+    return L == 32 || L == 64 || L == 96 || L == 100 || L == 128 || L == 192 || L == 200 || L == 256 || L == 400 ||
+           L == 500 || L == 512 || L == 1024;
+}
 
 hipError_t launch_fast_group(const PassDesc& proto, const GroupArgs& g, int mode, int kind, bool fp64, hipStream_t s) {
     if (g.nitems <= 0 || g.ntiles == 0) return hipSuccess;
@@ -165,6 +172,10 @@ hipError_t launch_fast_group(const PassDesc& proto, const GroupArgs& g, int mode
         case 256: return launch_fast_group_256(proto, g, mode, kind, fp64, s);
         case 512: return launch_fast_group_512(proto, g, mode, kind, fp64, s);
         case 1024: return launch_fast_group_1024(proto, g, mode, kind, fp64, s);
+        case 100: return launch_fast_group_100(proto, g, mode, kind, fp64, s);
+        case 200: return launch_fast_group_200(proto, g, mode, kind, fp64, s);
+        case 400: return launch_fast_group_400(proto, g, mode, kind, fp64, s);
+        case 500: return launch_fast_group_500(proto, g, mode, kind, fp64, s);
         default: return hipErrorInvalidValue;
     }
 }

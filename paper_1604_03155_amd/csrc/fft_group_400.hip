@@ -1,0 +1,6 @@
+// Grouped specialised FFT passes of length 400 (see fft_fast_impl.h).
+#include "fft_fast_impl.h"
+
+namespace vg {
+VG_FAST_GROUP_INSTANTIATE(400)
+}  // namespace vg

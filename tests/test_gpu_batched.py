@@ -252,3 +252,22 @@ def test_autotuned_plans_agree_with_default_layout(d, N, kernel, k, tune):
     assert (torch.linalg.vector_norm(ga - gb) / torch.linalg.vector_norm(ga)).item() <= 2e-6
     if info["pad_bytes"] == 256 and info["xcd_map"] == 1 and info["four_step_L1"] == 0 and not info["generic_passes"]:
         assert torch.equal(a, b)
+
+
+def test_batched_mixed_radix_lengths_equal_single_applies():
+    """Batches over the mixed-radix lengths (2N = 100, 200, 300, 400): grouped
+    launches where grouped kernels exist (300 launches per density), every
+    output bitwise equal to the single apply."""
+    say("mixed-radix batch")
+    vg = _vg()
+    torch = _torch()
+    specs = [(3, 50, "helmholtz", 12.0), (3, 50, "laplace", 0.0), (3, 100, "helmholtz", 25.0),
+             (3, 100, "helmholtz", 30.0), (3, 150, "laplace", 0.0), (2, 200, "helmholtz", 40.0),
+             (2, 200, "laplace", 0.0), (2, 100, "helmholtz", 20.0)]
+    plans = [vg.Plan(d, N, kind, k, precision="fp32") for d, N, kind, k in specs]
+    fs = [dev(random_density(1500 + i, d, N)) for i, (d, N, _, _) in enumerate(specs)]
+    ref = singles(plans, fs)
+    out = vg.apply_batched(plans, fs)
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(out, ref)):
+        assert torch.equal(a, b), i
