@@ -18,7 +18,12 @@
 // Launch geometry.  Column passes give 16 adjacent pencils (128-byte runs for
 // complex64) to a workgroup.  Workgroups are dispatched round-robin over the
 // 8 XCDs of gfx950; the block index is permuted so that consecutive tiles run
-// on the same XCD and share its L2 and TLB.
+// on the same XCD and share its L2 and TLB (and, in the fused passes, so that
+// tiles reading the same table entries run next to each other).
+//
+// Lengths: powers of two up to 1024 (rows and columns) and 8192 (rows), plus
+// the mixed-radix 96, 100, 192, 200, 300, 400, 500 and, for rows, 3200, 6400,
+// 12800 (one translation unit per length, fft_fast_<L>.hip).
 #pragma once
 
 #include <type_traits>
@@ -689,7 +694,8 @@ struct KindIO {
 //         of length 8192 (one 64 KiB row per workgroup otherwise; 2D N =
 //         4096: 0.136 -> 0.119 ms; the forward rows measured slower split).
 // A row pencil too large for 64 KiB of LDS as complex values (complex128
-// rows of length 8192) is exchanged as real and imaginary parts in turn.
+// rows of length 8192, complex64 rows of 12800) is exchanged as real and
+// imaginary parts in turn.
 template <typename R, int L, int MODE>
 constexpr bool row_needs_split() {
     return MODE == MODE_ROW && L * (int)sizeof(cplx<R>) > 65536;
