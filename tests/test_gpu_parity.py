@@ -391,8 +391,8 @@ def test_size_limits_of_2d_rows():
 
 
 @pytest.mark.parametrize("N,k,precisions", [(50, 20.0, ("fp32", "fp64")), (100, 40.0, ("fp32", "fp64")),
-                                            (150, 60.0, ("fp32", "fp64")), (200, 80.0, ("fp32",)),
-                                            (250, 100.0, ("fp32",))])
+                                            (150, 60.0, ("fp32", "fp64")), (200, 80.0, ("fp32", "fp64")),
+                                            (250, 100.0, ("fp32", "fp64"))])
 def test_paper_3d_grid_sizes_mixed_radix(N, k, precisions):
     """The 3D grid sizes of the paper's scattering runs (N = 50 to 250, so 2N
     = 100 to 500 = 2^a 3^b 5^c): length-specialised kernels with radix-3 and
