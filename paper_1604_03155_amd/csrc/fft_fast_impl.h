@@ -692,7 +692,10 @@ struct KindIO {
 //         a CU instead of 2 (length 512 at N = 256: 0.39 -> 0.34 ms; length
 //         1024 at N = 512: 3.61 -> 3.47 ms); also the complex64 inverse rows
 //         of length 8192 (one 64 KiB row per workgroup otherwise; 2D N =
-//         4096: 0.136 -> 0.119 ms; the forward rows measured slower split).
+//         4096: 0.136 -> 0.119 ms; the forward rows measured slower split)
+//         and of length 512 (21 instead of 38 KiB per workgroup, 4 instead
+//         of 2 waves per SIMD: 0.078 -> 0.072 ms at N = 256; the forward
+//         rows and the unfused columns of length 512 gain nothing split).
 // A row pencil too large for 64 KiB of LDS as complex values (complex128
 // rows of length 8192, complex64 rows of 12800) is exchanged as real and
 // imaginary parts in turn.
@@ -706,7 +709,8 @@ struct Policy {
     static constexpr bool twl = L * (int)sizeof(cplx<R>) <= 8192 && make_plan(L, kMaxRad<R>).n >= 2;
     static constexpr bool split =
         (sizeof(R) == 4 && MODE == MODE_COL && (FK == FK_FUSED || FK == FK_FUSED_DERIV) && (L == 512 || L == 1024)) ||
-        (sizeof(R) == 4 && MODE == MODE_ROW && FK == FK_INV && L >= 8192) || row_needs_split<R, L, MODE>();
+        (sizeof(R) == 4 && MODE == MODE_ROW && FK == FK_INV && (L == 512 || L >= 8192)) ||
+        row_needs_split<R, L, MODE>();
     // the two-output kinds (two spectra per thread) keep the default budget
     static constexpr int min_waves = (split && sizeof(R) == 4 && FK != FK_INV_GRAD && FK != FK_FUSED_GRAD) ? 3 : 1;
 };
