@@ -1029,6 +1029,12 @@ constexpr Shape shape_for(int L, int mode, int esize) {
     // rows whose single pencil exceeds 64 KiB exchange half values (split)
     const int les = (mode == MODE_ROW && L * esize > 65536) ? esize / 2 : esize;
     int C = mode == MODE_COL ? 16 : 8;
+    // length-400 columns (3D N = 200) take 8 pencils: 16-pencil tiles (53 KiB
+    // of LDS, 5 waves) leave room for 2 workgroups per CU, 8-pencil tiles for
+    // 4 (fused pass 0.39 -> 0.25 ms, apply 0.64 -> 0.47 ms); length 500
+    // measured slower with 8 (apply 1.04 -> 1.20 ms: 4 waves for 3.1 waves'
+    // work, 64-byte runs)
+    if (mode == MODE_COL && L == 400) C = 8;
     while (C > 1 && C * LP * les > 65536) C /= 2;
     if (C * LP * les > 65536 && L * les > 65536) return Shape{0, E, 0};  // one pencil does not fit
     while (C * L / E < 64 && C < 64 && 2 * C * LP * les <= 65536) C *= 2;
