@@ -1035,6 +1035,10 @@ constexpr Shape shape_for(int L, int mode, int esize) {
     // measured slower with 8 (apply 1.04 -> 1.20 ms: 4 waves for 3.1 waves'
     // work, 64-byte runs)
     if (mode == MODE_COL && L == 400) C = 8;
+    // complex64 rows of length 300 take 16 pencils (160 threads, 40 KiB of
+    // LDS) instead of 8 (80 threads, a quarter-full second wave): 3D N = 150
+    // apply 0.304 -> 0.296 ms
+    if (mode == MODE_ROW && L == 300 && esize == 8) C = 16;
     while (C > 1 && C * LP * les > 65536) C /= 2;
     if (C * LP * les > 65536 && L * les > 65536) return Shape{0, E, 0};  // one pencil does not fit
     while (C * L / E < 64 && C < 64 && 2 * C * LP * les <= 65536) C *= 2;
