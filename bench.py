@@ -69,8 +69,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="helmholtz3d_k20_n256")
-    ap.add_argument("--cpu-sample", type=int, default=20,
-                    help="oracle applies timed for cpu_baseline (0: skip); 20 is about 10 s on 16 host threads")
+    ap.add_argument("--cpu-sample", type=int, default=2,
+                    help="oracle applies timed for cpu_baseline (0: skip); one full-size apply is about 5-10 s "
+                         "on 16 host threads")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=10,
                     help="timed applies of the FP64 GPU path on the same density (0: skip)")
@@ -233,7 +234,8 @@ def main():
                 fp64["rel_l2"] = float(np.linalg.norm(g64 - ref) / np.linalg.norm(ref))
                 log(f"[bench] FP64 GPU path rel L2 vs oracle {fp64['rel_l2']:.2e}")
         if args.cpu_sample > 0:
-            threads = op._workers()
+            from oracle import fft as offt
+            threads = offt.threads()
             tc = time.perf_counter()
             for _ in range(args.cpu_sample):
                 oplan.apply(f64)
@@ -241,7 +243,7 @@ def main():
             result["cpu_baseline"] = {
                 "value": V / cpu_s, "unit": "grid pts/s", "cores": threads, "kind": "oracle",
                 "sample": f"{args.cpu_sample} full-size FP64 oracle applies of {args.workload} "
-                          f"({2 * N}^{d} scipy FFTs, workers={threads}); plan excluded",
+                          f"({2 * N}^{d} oracle FFTs, {threads} OpenMP threads); plan excluded",
             }
             log(f"[bench] oracle apply {cpu_s:.2f} s on {threads} threads")
     print(json.dumps(result), flush=True)

@@ -21,8 +21,11 @@ Green's functions"):
 * closed_form.py -- potentials and gradients of a normalised Gaussian source
                     (Section 5.1), written from their derivations, plus
                     independent radial quadratures used to pin them.
+* fft.c, fft.py  -- the oracle's own DFTs: a recursive mixed-radix Cooley-Tukey
+                    FFT in C (gcc, OpenMP over pencils) and the O(n^2)
+                    definition that pins it.
 
-Everything is float64 / complex128.  A library FFT (numpy.fft / scipy.fft) and
-a matrix product serve as steps; nothing is blocked, fused or reordered beyond
-the definitions written in each function's docstring.
+Everything is float64 / complex128.  The FFT above and a matrix product serve
+as steps; nothing is blocked, fused or reordered beyond the definitions written
+in each function's docstring.
 """

@@ -27,28 +27,22 @@ from __future__ import annotations
 import math
 
 import numpy as np
-import scipy.fft as sfft
 
+from . import fft as _fft
 from . import greens
 
 P_DEFAULT = 4
 
 
-def _workers():
-    """Threads for the library FFT: OMP_NUM_THREADS when set, else all cores."""
-    import os
-    env = os.environ.get("OMP_NUM_THREADS")
-    if env and env.isdigit() and int(env) > 0:
-        return int(env)
-    return max(1, os.cpu_count() or 1)
-
-
 def fftn(a, workers=None):
-    return sfft.fftn(a, workers=workers or _workers())
+    """Forward DFT over every axis: the oracle's own FFT (fft.c), pinned to the
+    O(n^2) definition at every transform length the method uses."""
+    return _fft.fftn(a, workers=workers)
 
 
 def ifftn(a, workers=None):
-    return sfft.ifftn(a, workers=workers or _workers())
+    """Inverse DFT over every axis, divided by the number of points."""
+    return _fft.ifftn(a, workers=workers)
 
 
 def grid_coords(N):
@@ -93,8 +87,8 @@ def kernel_spectrum(d, N, kernel, k=0.0, L=None, P=P_DEFAULT, h=None):
 
 def operator_T(Ghat, N):
     """Eq. (1): T = M^{-d} IDFT_M(Ghat), returned on the offsets |n_j| <= N-1 as
-    an array of shape (2N-1)^d whose centre element is n = 0.  numpy's inverse
-    FFT carries the M^{-d} factor."""
+    an array of shape (2N-1)^d whose centre element is n = 0.  The inverse
+    transform ifftn carries the M^{-d} factor."""
     d = Ghat.ndim
     t = ifftn(Ghat)
     idx = np.arange(-(N - 1), N)
