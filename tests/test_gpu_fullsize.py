@@ -20,6 +20,8 @@ import sys
 import numpy as np
 import pytest
 
+from parity import check, rel_l2  # noqa: E402
+
 pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-12
@@ -31,8 +33,6 @@ def say(*a):
     sys.stdout.flush()
 
 
-def rel_l2(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
 _CACHE = {}
@@ -61,9 +61,7 @@ def test_laplace3d_n32_fp64_oracle_and_closed_form():
     N = prm["N"]
     p = vg.Plan(3, N, "laplace", precision="fp64")
     phi = p.apply(torch.from_numpy(f).cuda()).cpu().numpy()
-    e = rel_l2(phi, o.apply(f))
-    say("  fp64 vs oracle", e)
-    assert e <= FP64_TOL
+    check(phi, o.apply(f), FP64_TOL, "fp64 vs oracle")
     x = grid_coords(N)
     pts = np.stack(np.meshgrid(x, x, x, indexing="ij"), axis=-1).reshape(-1, 3)
     u = cf.gaussian_sum_potential(3, "laplace", 0.0, src.centers, src.sigmas, src.amps, pts)
@@ -92,9 +90,7 @@ def test_helmholtz3d_full_size_fp32_and_fp64(name):
         out = torch.empty_like(x)
         p.apply(x, out=out, workspace=ws)
         torch.cuda.synchronize()
-        e = rel_l2(out.cpu().numpy(), ref)
-        say("  ", precision, "apply rel L2", e)
-        assert e <= tol
+        check(out.cpu().numpy(), ref, tol, f"{precision} apply")
         del p, x, ws, out
         torch.cuda.empty_cache()
 
@@ -112,9 +108,7 @@ def test_helmholtz3d_n256_fp32_gradient_reuse_and_in_place():
     torch.cuda.synchronize()
     gref = o.gradient(f)
     for j in range(3):
-        e = rel_l2(grad[j].cpu().numpy(), gref[j])
-        say("   grad", j, e)
-        assert e <= FP32_TOL
+        check(grad[j].cpu().numpy(), gref[j], FP32_TOL, f"grad {j}")
     del grad
     # a second density through the same workspace, then in place
     rng = np.random.default_rng(256)
@@ -127,7 +121,7 @@ def test_helmholtz3d_n256_fp32_gradient_reuse_and_in_place():
     p.apply(y, out=out2, workspace=ws)
     p.apply(y, out=y, workspace=ws)
     torch.cuda.synchronize()
-    assert rel_l2(out.cpu().numpy(), o.apply(f)) <= FP32_TOL
+    check(out.cpu().numpy(), o.apply(f), FP32_TOL)
     ref_g = o.apply(g)
-    assert rel_l2(out2.cpu().numpy(), ref_g) <= FP32_TOL
+    check(out2.cpu().numpy(), ref_g, FP32_TOL)
     assert torch.equal(out2, y)

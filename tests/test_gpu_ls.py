@@ -7,6 +7,8 @@ import time
 import numpy as np
 import pytest
 
+from parity import check, rel_l2  # noqa: E402
+
 pytestmark = pytest.mark.gpu
 
 
@@ -15,8 +17,6 @@ def say(*a):
     sys.stdout.flush()
 
 
-def rel_l2(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
 def _dev(a, precision):
@@ -44,11 +44,10 @@ def test_ls_solve_matches_direct_solve(d, N, name, k, precision, tol, bound):
     p = vg.Plan(d, N, "helmholtz", k, precision=precision)
     sigma, info = p.ls_solve(_dev(q, precision), _dev(pin, precision), tol=tol, max_iter=400)
     torch.cuda.synchronize()
-    err = rel_l2(sigma.cpu().numpy(), ref)
-    say("  ", info, "vs direct", err)
+    say("  ", info)
     assert info["converged"] == 1 and info["residual"] <= tol
     assert info["matvecs"] <= 2 * info["iterations"]
-    assert err <= bound
+    check(sigma.cpu().numpy(), ref, bound, "vs direct solve")
 
 
 def test_ls_large_grids_self_convergence_and_oracle_residual():
