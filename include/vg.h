@@ -78,10 +78,18 @@ typedef enum vg_precision {
 
 /* Plan-time autotuning: the apply program is timed (on zero arrays, on the
  * plan's stream, synchronously) under candidate layouts and the fastest is
- * kept for apply and gradient.  Candidates: pitch padding of the 2N x 2N
- * planes (3D) / 2N rows (2D) of the intermediates, XCD-aware tile order of
- * the specialised kernels, the four-step split 2N = L1 L2 of long 2D columns,
- * and (full) every pass on the generic runtime-radix kernel. */
+ * kept for apply and gradient.  Candidates: the plan's default layout, pitch
+ * padding of the 2N x 2N planes (3D) / 2N rows (2D) of the intermediates,
+ * XCD-aware tile order of the specialised kernels, the four-step split
+ * 2N = L1 L2 of long 2D columns, and (full) every pass on the generic
+ * runtime-radix kernel.
+ * The choice is persisted in a JSON file ($VG_TUNE_CACHE; empty disables it;
+ * default $XDG_CACHE_HOME/vgconv/tune.json or ~/.cache/vgconv/tune.json)
+ * under a key of (d, N, table class, precision, tune mode, device
+ * architecture and compute units, library build); a later plan with the same
+ * key takes the stored layout without timing.  A missing, corrupt or stale
+ * file means tuning as without a cache; a file that cannot be written is
+ * ignored. */
 typedef enum vg_tune_mode {
     VG_TUNE_OFF = 0,    /* built-in layout: 256-byte padding, XCD order, default split */
     VG_TUNE_QUICK = 1,  /* padding {256, 0} x order {XCD, launch} (x 3 splits in 2D), 3 timed applies each */
@@ -119,6 +127,7 @@ typedef struct vg_plan_info {
     int xcd_map;              /* 1: XCD-aware tile order */
     int four_step_L1;         /* four-step split of long 2D columns (0: default / none) */
     int generic_passes;       /* 1: all passes on the generic kernel */
+    int tune_cached;          /* 1: the layout was read from the persistent tune cache (no timing) */
 } vg_plan_info;
 
 /*
@@ -210,7 +219,12 @@ vg_status vg_apply_real(const vg_plan* plan, const void* f, void* phi, void* wor
  * later calls with the same arguments (the library keeps the last 8 such
  * batches; destroying a plan drops the batches that use it).
  * The call may itself be recorded into the caller's stream capture once the
- * same arguments have been used in one call outside capture.
+ * same arguments have been used in one call outside capture.  The recorded
+ * launches point into device memory the library keeps for that batch (its
+ * descriptors and, with workspace == NULL, the internal workspace): such a
+ * batch is never evicted from the cache and keeps that memory until one of
+ * its plans is destroyed, after which the caller's graph must not be
+ * launched again.
  * workspace: at least vg_batched_workspace_size bytes, or NULL (an internal
  * buffer owned by the library; such calls must not overlap in time).
  * Errors: VG_ERR_INVALID_ARG (count <= 0, NULL entries, mixed precision, a

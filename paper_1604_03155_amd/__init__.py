@@ -17,7 +17,7 @@ import ctypes
 import os
 
 __all__ = [
-    "LIBRARY_PATH", "VGError", "Plan", "apply_batched", "batched_workspace_size",
+    "LIBRARY_PATH", "VGError", "Plan", "apply_batched", "batched_workspace_size", "check_workspace",
     "LAPLACE", "HELMHOLTZ", "FP32", "FP64", "status_string", "profiler_enable", "profiler_collect", "hbm_copy",
 ]
 
@@ -53,7 +53,7 @@ class _Info(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_size_t), ("gradient_workspace_bytes", ctypes.c_size_t),
                 ("tune", ctypes.c_int), ("tune_ms", ctypes.c_double), ("tune_candidates", ctypes.c_int),
                 ("pad_bytes", ctypes.c_int), ("xcd_map", ctypes.c_int), ("four_step_L1", ctypes.c_int),
-                ("generic_passes", ctypes.c_int)]
+                ("generic_passes", ctypes.c_int), ("tune_cached", ctypes.c_int)]
 
 
 class _LsResult(ctypes.Structure):
@@ -127,6 +127,30 @@ def _stream_ptr(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def check_workspace(ws, need, device_index=None):
+    """Validate a caller workspace: a contiguous, 256-byte aligned tensor of at
+    least `need` bytes on the CUDA device `device_index` (None: any).  Returns
+    its device pointer as a ctypes void pointer, or None for ws None (the
+    library's own buffer)."""
+    if ws is None:
+        return None
+    torch = _torch()
+    if not isinstance(ws, torch.Tensor):
+        raise TypeError("workspace must be a torch tensor")
+    nbytes = ws.numel() * ws.element_size()
+    if nbytes < need:
+        raise ValueError(f"workspace holds {nbytes} bytes; this call needs {need}")
+    if not ws.is_contiguous():
+        raise ValueError("workspace must be contiguous")
+    if not ws.is_cuda:
+        raise ValueError("workspace must be a CUDA tensor")
+    if device_index is not None and ws.device.index != device_index:
+        raise ValueError(f"workspace is on cuda:{ws.device.index}, the arrays on cuda:{device_index}")
+    if ws.data_ptr() % 256:
+        raise ValueError("workspace must be 256-byte aligned")
+    return _vp(ws.data_ptr())
 
 
 class Plan:
@@ -209,7 +233,7 @@ class Plan:
         if out is None:
             out = torch.empty_like(f)
         self._check_array(out, "out")
-        ws = _vp(workspace.data_ptr()) if workspace is not None else None
+        ws = check_workspace(workspace, self.workspace_size(), f.device.index)
         _check(_lib.vg_apply(self._h, _vp(f.data_ptr()), _vp(out.data_ptr()), ws, _stream_ptr(stream)), "vg_apply")
         return out
 
@@ -224,7 +248,7 @@ class Plan:
             phi = torch.empty_like(f)
         if phi is not None:
             self._check_array(phi, "phi")
-        ws = _vp(workspace.data_ptr()) if workspace is not None else None
+        ws = check_workspace(workspace, self.workspace_size(gradient=True), f.device.index)
         _check(_lib.vg_gradient(self._h, _vp(f.data_ptr()), _vp(phi.data_ptr()) if phi is not None else None,
                                 _vp(grad.data_ptr()), ws, _stream_ptr(stream)), "vg_gradient")
         return phi, grad
@@ -243,7 +267,7 @@ class Plan:
                 raise ValueError(f"{name} must be a contiguous {rdt} tensor of shape {self.shape}")
         if out is None:
             out = torch.empty_like(f)
-        ws = _vp(workspace.data_ptr()) if workspace is not None else None
+        ws = check_workspace(workspace, self.real_workspace_size(), f.device.index)
         _check(_lib.vg_apply_real(self._h, _vp(f.data_ptr()), _vp(out.data_ptr()), ws, _stream_ptr(stream)),
                "vg_apply_real")
         return out
@@ -262,7 +286,7 @@ class Plan:
             sigma = torch.empty_like(phi_in)
         self._check_array(sigma, "sigma")
         res = _LsResult()
-        ws = _vp(workspace.data_ptr()) if workspace is not None else None
+        ws = check_workspace(workspace, self.ls_workspace_size(), q.device.index)
         _check(_lib.vg_ls_solve(self._h, _vp(q.data_ptr()), _vp(phi_in.data_ptr()), _vp(sigma.data_ptr()),
                                 float(tol), int(max_iter), ws, _stream_ptr(stream), ctypes.byref(res)), "vg_ls_solve")
         return sigma, {f: getattr(res, f) for f, _ in _LsResult._fields_}
@@ -338,6 +362,6 @@ def apply_batched(plans, fs, outs=None, workspace=None, stream=None):
     n = len(plans)
     fa = (_vp * n)(*[f.data_ptr() for f in fs])
     oa = (_vp * n)(*[o.data_ptr() for o in outs])
-    ws = _vp(workspace.data_ptr()) if workspace is not None else None
+    ws = check_workspace(workspace, batched_workspace_size(plans), fs[0].device.index if fs else None)
     _check(_lib.vg_apply_batched(n, _handles(plans), fa, oa, ws, _stream_ptr(stream)), "vg_apply_batched")
     return outs

@@ -186,6 +186,7 @@ vg_status vg_plan_get_info(const vg_plan* p, vg_plan_info* info) {
     info->xcd_map = p->cfg.xcd_map;
     info->four_step_L1 = p->cfg.fs_L1;
     info->generic_passes = p->cfg.generic;
+    info->tune_cached = p->tune_cached;
     return VG_OK;
 }
 

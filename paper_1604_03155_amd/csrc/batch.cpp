@@ -17,6 +17,7 @@
 #include <memory>
 #include <tuple>
 
+#include "batch_cache.h"
 #include "plan.h"
 
 namespace vg {
@@ -35,6 +36,18 @@ struct BatchLaunch {
     const char* name = nullptr;
 };
 
+// The library's internal batched workspace (calls with workspace == NULL).
+// Entries that use it hold a reference, so a buffer replaced by a larger one
+// stays allocated while a pinned entry (recorded into a caller's graph)
+// still points into it.
+struct DevBlock {
+    void* p = nullptr;
+    size_t bytes = 0;
+    ~DevBlock() {
+        if (p) (void)hipFree(p);
+    }
+};
+
 struct BatchEntry {
     std::vector<const vg_plan*> plans;
     std::vector<const void*> f;
@@ -48,6 +61,8 @@ struct BatchEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool graph_failed = false;
+    bool pinned = false;                  // recorded into a caller's capture: never evicted
+    std::shared_ptr<DevBlock> ws_hold;    // the internal workspace block, when ws points into it
 
     ~BatchEntry() {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -59,10 +74,12 @@ struct BatchEntry {
 constexpr size_t kMaxEntries = 8;
 
 std::mutex g_batch_mutex;
-void* g_batch_ws = nullptr;
-size_t g_batch_ws_bytes = 0;
-std::list<std::unique_ptr<BatchEntry>> g_entries;  // most recently used first
-std::map<int, hipStream_t> g_capture_streams;      // per device
+std::shared_ptr<DevBlock> g_batch_ws;           // internal workspace
+BatchCache<BatchEntry> g_entries;               // most recently used first
+std::map<int, hipStream_t> g_capture_streams;   // per device
+
+// a dropped entry's graph may still be running
+void sync_device() { (void)hipDeviceSynchronize(); }
 
 long long tiles_of(const PassDesc& d, int mode) {
     return mode == MODE_COL ? (long long)d.outer * ((d.inner + d.C - 1) / d.C) : ((long long)d.outer + d.C - 1) / d.C;
@@ -220,13 +237,6 @@ bool same_key(const BatchEntry& e, int count, const vg_plan* const* plans, const
     return true;
 }
 
-// Drop entries until at most `keep` remain (oldest first); waits for the
-// device first since a dropped entry's graph may still be running.
-void trim(size_t keep) {
-    if (g_entries.size() <= keep) return;
-    (void)hipDeviceSynchronize();
-    while (g_entries.size() > keep) g_entries.pop_back();
-}
 }  // namespace
 
 int fft_max_lds_bytes_for_device() {
@@ -245,14 +255,10 @@ size_t batched_workspace_size(int count, const vg_plan* const* plans) {
 
 void batched_release_plan(const vg_plan* p) {
     std::lock_guard<std::mutex> lk(g_batch_mutex);
-    bool any = false;
-    for (auto& e : g_entries)
-        if (std::find(e->plans.begin(), e->plans.end(), p) != e->plans.end()) any = true;
-    if (!any) return;
-    (void)hipDeviceSynchronize();
-    g_entries.remove_if([&](const std::unique_ptr<BatchEntry>& e) {
-        return std::find(e->plans.begin(), e->plans.end(), p) != e->plans.end();
-    });
+    // pinned entries too: a caller's graph that recorded a batch with this
+    // plan is invalid once the plan (its tables) is gone
+    g_entries.drop_if([&](const BatchEntry& e) { return std::find(e.plans.begin(), e.plans.end(), p) != e.plans.end(); },
+                      sync_device);
 }
 
 vg_status batched_apply(int count, const vg_plan* const* plans, const void* const* f, void* const* phi,
@@ -272,51 +278,51 @@ vg_status batched_apply(int count, const vg_plan* const* plans, const void* cons
     const size_t need = batched_workspace_size(count, plans);
     void* ws = workspace;
     if (!ws) {
-        if (g_batch_ws_bytes < need) {
+        if (!g_batch_ws || g_batch_ws->bytes < need) {
             if (capturing) return fail(VG_ERR_NOT_CAPTURABLE, "batched call under capture needs a workspace allocation");
-            trim(0);  // entries may point into the old buffer
-            if (g_batch_ws) (void)hipFree(g_batch_ws);
-            g_batch_ws = nullptr;
-            g_batch_ws_bytes = 0;
-            he = dev_malloc(&g_batch_ws, need);
+            // unpinned entries on the old buffer go; pinned ones keep it alive
+            if (g_batch_ws) {
+                DevBlock* old = g_batch_ws.get();
+                g_entries.evict_if([&](const BatchEntry& x) { return x.ws_hold.get() == old; }, sync_device);
+                sync_device();
+            }
+            auto blk = std::make_shared<DevBlock>();
+            he = dev_malloc(&blk->p, need);
             if (he != hipSuccess) return from_hip(he, "batched workspace");
-            g_batch_ws_bytes = need;
+            blk->bytes = need;
+            g_batch_ws = blk;
         }
-        ws = g_batch_ws;
+        ws = g_batch_ws->p;
     }
 
-    BatchEntry* e = nullptr;
-    for (auto it = g_entries.begin(); it != g_entries.end(); ++it) {
-        if (same_key(**it, count, plans, f, phi, ws, dev)) {
-            g_entries.splice(g_entries.begin(), g_entries, it);
-            e = g_entries.front().get();
-            break;
-        }
-    }
+    BatchEntry* e = g_entries.find(
+        [&](const BatchEntry& x) { return same_key(x, count, plans, f, phi, ws, dev); });
     if (!e) {
         if (capturing)
             return fail(VG_ERR_NOT_CAPTURABLE,
                         "first batched call with these plans and arrays must run outside stream capture");
-        trim(kMaxEntries - 1);
+        g_entries.trim(kMaxEntries - 1, sync_device);
         auto ne = std::make_unique<BatchEntry>();
         ne->plans.assign(plans, plans + count);
         ne->f.assign(f, f + count);
         ne->phi.assign(phi, phi + count);
         ne->ws = ws;
+        if (!workspace) ne->ws_hold = g_batch_ws;
         ne->device = dev;
         ne->fp64 = plans[0]->fp64;
         vg_status st = build_entry(*ne);
         if (st != VG_OK) return st;
         if (env_flag("VG_BATCH_NO_GRAPH") || capture(*ne) != VG_OK) ne->graph_failed = true;
-        g_entries.push_front(std::move(ne));
-        e = g_entries.front().get();
+        e = g_entries.push_front(std::move(ne));
     }
 
     void* mark = capturing ? nullptr : profiler_mark(stream);
     if (capturing || !e->exec) {
-        // the caller's own capture records the launches; or no graph
+        // the caller's own capture records the launches (which point into
+        // this entry's descriptors and workspace: pin it); or no graph
         vg_status st = issue(*e, stream);
         if (st != VG_OK) return st;
+        if (capturing) e->pinned = true;
     } else {
         he = hipGraphLaunch(e->exec, stream);
         if (he != hipSuccess) return from_hip(he, "graph launch");

@@ -58,6 +58,7 @@ struct vg_plan {
     vg::LayoutConfig cfg;
     double tune_ms = 0.0;     // wall time of the autotuner
     int tune_candidates = 0;  // configurations timed
+    int tune_cached = 0;      // 1: the layout came from the persistent tune cache
     double k = 0.0, L = 0.0;
     double h[3] = {0.0, 0.0, 0.0};  // convection vector (VG_CONVECTION)
     int device = 0;

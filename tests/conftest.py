@@ -8,6 +8,19 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
+@pytest.fixture(scope="session", autouse=True)
+def _private_tune_cache(tmp_path_factory):
+    """Tuned plans made by the tests write their layout cache to a scratch
+    file of the session, never to the user's cache directory."""
+    old = os.environ.get("VG_TUNE_CACHE")
+    os.environ["VG_TUNE_CACHE"] = str(tmp_path_factory.mktemp("tune") / "tune.json")
+    yield
+    if old is None:
+        os.environ.pop("VG_TUNE_CACHE", None)
+    else:
+        os.environ["VG_TUNE_CACHE"] = old
+
+
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")

@@ -4,12 +4,15 @@ The batch runs stage by stage with grouped launches (one launch per stage and
 kernel shape, workgroups taking (density, tile) items) captured in a HIP graph.
 Every tile runs the same code as in a single-plan apply, so batched results
 must equal single applies bit for bit; a sample of the mixed 64-density batch
-is also checked against the FP64 oracle at the FP32 bar (relative L2 1e-5).
+is also checked against the FP64 oracle at the FP32 bar (relative L2 and
+relative max error 1e-5).
 """
 import sys
 
 import numpy as np
 import pytest
+
+from parity import check  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -31,8 +34,6 @@ def _torch():
     return torch
 
 
-def rel_l2(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
 def random_density(seed, d, N):
@@ -97,7 +98,7 @@ def test_c4_batch_sample_against_oracle(c4):
         prm = items[i][0]
         say("  oracle", i, N, kernel, prm["k"])
         o = op.Plan(3, N, kernel, prm["k"])
-        assert rel_l2(out[i].cpu().numpy(), o.apply(fs_host[i])) <= FP32_TOL, i
+        check(out[i].cpu().numpy(), o.apply(fs_host[i]), FP32_TOL, i)
 
 
 def test_c4_graph_replays_track_new_density_values(c4):
@@ -229,11 +230,12 @@ def test_batched_first_call_under_capture_is_refused():
 
 @pytest.mark.parametrize("d,N,kernel,k,tune", [(3, 64, "helmholtz", 20.0, "quick"), (3, 48, "laplace", 0.0, "full"),
                                                (2, 2048, "laplace", 0.0, "quick"), (2, 128, "helmholtz", 30.0, "full")])
-def test_autotuned_plans_agree_with_default_layout(d, N, kernel, k, tune):
+def test_autotuned_plans_agree_with_default_layout(d, N, kernel, k, tune, monkeypatch):
     """Plans built with the autotuner (timed layouts: pitch padding, tile
     order, four-step split, generic kernels) compute the same operator: equal
     to the default plan to FP32 rounding, bitwise when the default layout won."""
     say("autotune", d, N, kernel, k, tune)
+    monkeypatch.setenv("VG_TUNE_CACHE", "")  # always time here: no persistent cache
     vg = _vg()
     torch = _torch()
     f = dev(random_density(120 + N, d, N))
@@ -271,3 +273,48 @@ def test_batched_mixed_radix_lengths_equal_single_applies():
     torch.cuda.synchronize()
     for i, (a, b) in enumerate(zip(out, ref)):
         assert torch.equal(a, b), i
+
+
+def test_tune_cache_reuses_the_choice(tmp_path, monkeypatch):
+    """The autotuner's persistent cache: the first tuned plan times its
+    candidates and stores the choice; a second plan with the same key takes it
+    without timing and computes bit for bit the same; a corrupt file or a
+    stale entry (another library build) makes the next plan tune again."""
+    import json
+    vg = _vg()
+    torch = _torch()
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("VG_TUNE_CACHE", str(path))
+    fields = ("pad_bytes", "xcd_map", "four_step_L1", "generic_passes")
+    f = dev(random_density(77, 3, 64))
+    p1 = vg.Plan(3, 64, "helmholtz", 20.0, tune="quick")
+    say("  first", p1.info["tune_cached"], p1.info["tune_candidates"], p1.info["tune_ms"])
+    assert p1.info["tune_cached"] == 0 and p1.info["tune_candidates"] >= 4
+    doc = json.loads(path.read_text())
+    assert doc["format"] == "vgconv-tune-1" and len(doc["entries"]) == 1
+    key = next(iter(doc["entries"]))
+    assert "d=3;N=64;table=complex;precision=fp32;mode=quick" in key
+    p2 = vg.Plan(3, 64, "helmholtz", 7.0, tune="quick")  # same key: k does not enter it
+    say("  second", p2.info["tune_cached"], p2.info["tune_candidates"], p2.info["tune_ms"])
+    assert p2.info["tune_cached"] == 1 and p2.info["tune_candidates"] == 0
+    assert all(p2.info[x] == p1.info[x] for x in fields)
+    p3 = vg.Plan(3, 64, "helmholtz", 20.0, tune="quick")
+    a, b = p1.apply(f), p3.apply(f)
+    torch.cuda.synchronize()
+    assert p3.info["tune_cached"] == 1 and torch.equal(a, b)
+    # corrupt file: tuned again, file rewritten
+    path.write_text('{"format": "vgconv-tune-1", "entries": {')
+    p4 = vg.Plan(3, 64, "helmholtz", 20.0, tune="quick")
+    assert p4.info["tune_cached"] == 0 and p4.info["tune_candidates"] >= 4
+    assert key in json.loads(path.read_text())["entries"]
+    # stale entry: the same grid under another library build is not reused
+    doc = json.loads(path.read_text())
+    doc["entries"] = {key.rsplit("build=", 1)[0] + "build=0000000000000000": doc["entries"][key]}
+    path.write_text(json.dumps(doc))
+    p5 = vg.Plan(3, 64, "helmholtz", 20.0, tune="quick")
+    assert p5.info["tune_cached"] == 0 and p5.info["tune_candidates"] >= 4
+    # an unwritable location (below a regular file) is not an error
+    (tmp_path / "afile").write_text("x")
+    monkeypatch.setenv("VG_TUNE_CACHE", str(tmp_path / "afile" / "tune.json"))
+    p6 = vg.Plan(3, 32, "laplace", 0.0, tune="quick")
+    assert p6.info["tune_candidates"] >= 1
