@@ -208,6 +208,28 @@ size_t vg_real_workspace_size(const vg_plan* plan);
 vg_status vg_apply_real(const vg_plan* plan, const void* f, void* phi, void* workspace, void* stream);
 
 /*
+ * Allocation-free apply, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Computes exactly what vg_apply computes (the same kernels and
+ * launches; results are bit-identical), with its workspace in a device array
+ * owned by the library: VG_NOALLOC_WORKSPACE_BYTES (128 MiB) per GPU, held
+ * from library load until the process ends.  The call allocates nothing; the
+ * array's device address is looked up once per device, on the first call
+ * made with that device current.  The caller passes f and phi as for
+ * vg_apply (device arrays of N^d complex; phi == f allowed).
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind: calls that overlap in time on one GPU (different streams or host
+ * threads) race and give wrong results.  No pass reads workspace it has not
+ * written in the same call, so nothing needs clearing between calls.
+ * Errors: VG_ERR_INVALID_ARG (NULL arguments, a plan of another device),
+ * VG_ERR_UNSUPPORTED_SIZE (vg_workspace_size(plan) above
+ * VG_NOALLOC_WORKSPACE_BYTES: e.g. 3D N > 128 in FP32, N > 96 in FP64),
+ * VG_ERR_DEVICE (symbol lookup, launch).
+ */
+#define VG_NOALLOC_WORKSPACE_BYTES (128u << 20)
+vg_status vg_apply_noalloc(const vg_plan* plan, const void* f, void* phi, void* stream);
+
+/*
  * Apply `count` plans to `count` densities in one go: phi[i] = T_i * f[i]
  * (Section 4 applied to a set of independent densities).  Plans may mix d, N,
  * kernel and k; all must share one precision and live on the current device.

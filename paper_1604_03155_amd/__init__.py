@@ -76,6 +76,7 @@ _sig = {
     "vg_workspace_size": (ctypes.c_size_t, [_vp]),
     "vg_gradient_workspace_size": (ctypes.c_size_t, [_vp]),
     "vg_apply": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "vg_apply_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "vg_gradient": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "vg_batched_workspace_size": (ctypes.c_size_t, [ctypes.c_int, ctypes.POINTER(_vp)]),
     "vg_apply_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
@@ -235,6 +236,16 @@ class Plan:
         self._check_array(out, "out")
         ws = check_workspace(workspace, self.workspace_size(), f.device.index)
         _check(_lib.vg_apply(self._h, _vp(f.data_ptr()), _vp(out.data_ptr()), ws, _stream_ptr(stream)), "vg_apply")
+        return out
+
+    def apply_noalloc(self, f, out, stream=None):
+        """phi = T * f like apply(), with no device allocation: the workspace is
+        the library's fixed per-GPU array (plans up to VG_NOALLOC_WORKSPACE_BYTES
+        of workspace); calls that overlap on one GPU race."""
+        self._check_array(f, "f")
+        self._check_array(out, "out")
+        _check(_lib.vg_apply_noalloc(self._h, _vp(f.data_ptr()), _vp(out.data_ptr()), _stream_ptr(stream)),
+               "vg_apply_noalloc")
         return out
 
     def gradient(self, f, with_phi=True, phi=None, grad=None, workspace=None, stream=None):

@@ -850,11 +850,10 @@ void finalize_bytes(vg_plan* p) {
         for (PassStep& s : pr->steps) s.bytes = pass_bytes(p, s);
 }
 
-std::vector<BoundStep> bind_program(const vg_plan* p, const Program& prog, const void* f, void* phi, void* grad,
-                                    void* ws) {
-    const long long N = p->N;
+BoundStep bind_step(const vg_plan* p, const Program& prog, const PassStep& st, const void* f, void* phi, void* grad,
+                    void* ws) {
     long long V = 1;
-    for (int i = 0; i < p->d; ++i) V *= N;
+    for (int i = 0; i < p->d; ++i) V *= p->N;
     const size_t es = p->fp64 ? 16 : 8;
     auto resolve = [&](int id) -> void* {
         if (id == BUF_F) return const_cast<void*>(f);
@@ -864,27 +863,30 @@ std::vector<BoundStep> bind_program(const vg_plan* p, const Program& prog, const
         if (id >= BUF_WS0 && id < BUF_WS0 + 8) return static_cast<unsigned char*>(ws) + prog.ws_offsets[id - BUF_WS0];
         return nullptr;
     };
+    BoundStep b;
+    b.desc = st.desc;
+    b.desc.table = p->table;  // programs are built before the precompute fills the table
+    b.desc.in = resolve(st.in_buf);
+    b.desc.out = resolve(st.out_buf);
+    b.desc.out2 = resolve(st.out2_buf);
+    b.kind = st.kind;
+    if (b.kind == KIND_INV_GRAD && b.desc.out == nullptr) {
+        // gradient without phi: derivative-only inverse into out2
+        b.desc.out = b.desc.out2;
+        b.desc.out2 = nullptr;
+        b.kind = 100 + KIND_INV;
+    }
+    b.mode = st.mode;
+    b.name = st.name;
+    b.bytes = st.bytes;
+    return b;
+}
+
+std::vector<BoundStep> bind_program(const vg_plan* p, const Program& prog, const void* f, void* phi, void* grad,
+                                    void* ws) {
     std::vector<BoundStep> out;
     out.reserve(prog.steps.size());
-    for (const PassStep& st : prog.steps) {
-        BoundStep b;
-        b.desc = st.desc;
-        b.desc.table = p->table;  // programs are built before the precompute fills the table
-        b.desc.in = resolve(st.in_buf);
-        b.desc.out = resolve(st.out_buf);
-        b.desc.out2 = resolve(st.out2_buf);
-        b.kind = st.kind;
-        if (b.kind == KIND_INV_GRAD && b.desc.out == nullptr) {
-            // gradient without phi: derivative-only inverse into out2
-            b.desc.out = b.desc.out2;
-            b.desc.out2 = nullptr;
-            b.kind = 100 + KIND_INV;
-        }
-        b.mode = st.mode;
-        b.name = st.name;
-        b.bytes = st.bytes;
-        out.push_back(b);
-    }
+    for (const PassStep& st : prog.steps) out.push_back(bind_step(p, prog, st, f, phi, grad, ws));
     return out;
 }
 
@@ -919,5 +921,17 @@ vg_status run_program(const vg_plan* p, const Program& prog, const void* f, void
     return VG_OK;
 }
 
+
+// The same launches as run_program with no host containers and no profiler
+// events: the path of the allocation-free entry point.
+vg_status run_program_noalloc(const vg_plan* p, const Program& prog, const void* f, void* phi, void* grad, void* ws,
+                              hipStream_t stream) {
+    for (const PassStep& ps : prog.steps) {
+        const BoundStep st = bind_step(p, prog, ps, f, phi, grad, ws);
+        hipError_t e = launch_fft_pass(st.desc, st.mode, st.kind, p->fp64, stream);
+        if (e != hipSuccess) return from_hip(e, st.name);
+    }
+    return VG_OK;
+}
 
 }  // namespace vg

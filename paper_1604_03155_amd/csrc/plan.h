@@ -109,12 +109,17 @@ struct BoundStep {
     const char* name;
     double bytes;
 };
+BoundStep bind_step(const vg_plan* p, const Program& prog, const PassStep& st, const void* f, void* phi, void* grad,
+                    void* ws);
 std::vector<BoundStep> bind_program(const vg_plan* p, const Program& prog, const void* f, void* phi, void* grad,
                                     void* ws);
 
 // Run a program: bind buffers and launch every step on `stream`.
 vg_status run_program(const vg_plan* p, const Program& prog, const void* f, void* phi, void* grad,
                       void* ws, hipStream_t stream);
+// The same launches without host containers or profiler events.
+vg_status run_program_noalloc(const vg_plan* p, const Program& prog, const void* f, void* phi, void* grad,
+                              void* ws, hipStream_t stream);
 
 
 // Pass profiler hooks (profiler.cpp).
