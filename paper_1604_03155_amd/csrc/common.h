@@ -107,9 +107,10 @@ struct PassDesc {
     // 1: the table covers every spectral index of the L^d box (no octant
     // fold): flat = k * L^(d-1) + column (convection kernel)
     int table_full;
-    // specialised kernels: 1 when every column tile row starts on a 128-byte
-    // line (pitches multiples of 128 bytes) or the pass is a row pass, so
-    // streaming loads and stores cover whole lines
+    // specialised kernels: bit 0 streaming (non-temporal) loads, bit 1
+    // streaming stores; allowed when every column tile row starts on a
+    // 128-byte line (pitches multiples of 128 bytes) or the pass is a row
+    // pass, so that they cover whole lines
     int stream;
 };
 

@@ -305,7 +305,7 @@ struct FTile {
     int nvalid;
     int col0;
     int o;                  // outer index (column tiles)
-    int stream;             // streaming access allowed (PassDesc::stream)
+    int stream;             // streaming access allowed (PassDesc::stream: 1 loads, 2 stores)
 };
 
 // XCD-aware order for one-tile-per-workgroup launches: dispatch slot b runs
@@ -399,7 +399,7 @@ __device__ __forceinline__ void issue_loads(cplx<R>* vn, const cplx<R>* __restri
             }
         }
     };
-    if (streaming_loads<R, C, MODE>() && tl.stream) body(std::true_type{});
+    if (streaming_loads<R, C, MODE>() && (tl.stream & 1)) body(std::true_type{});
     else body(std::false_type{});
 }
 
@@ -455,7 +455,7 @@ __device__ __forceinline__ void store_global_t(const cplx<R>* v, cplx<R>* __rest
             }
         }
     };
-    if (streaming_stores<R, C, MODE>() && tl.stream) body(std::true_type{});
+    if (streaming_stores<R, C, MODE>() && (tl.stream & 2)) body(std::true_type{});
     else body(std::false_type{});
 }
 

@@ -808,7 +808,7 @@ vg_status build_programs(vg_plan* p, hipStream_t stream) {
                 auto al = [&](long long x) { return (x * es) % 128 == 0; };
                 st.desc.stream = (st.mode == MODE_ROW || (al(st.desc.in_se) && al(st.desc.out_se) &&
                                                           al(st.desc.in_so) && al(st.desc.out_so)))
-                                     ? 1
+                                     ? 3
                                      : 0;
             }
             st.desc.table_full = p->kernel == VG_CONVECTION ? 1 : 0;
