@@ -278,16 +278,20 @@ vg_status vg_plan_kernel_hat(const vg_plan* p, double* host_out) {
         if (e != hipSuccess) return from_hip(e, "table download");
         double sc = 1.0;
         for (int i = 0; i < p->d; ++i) sc *= 2.0 * p->N;
+        // 3D octant rows are padded to tab_pitch entries
+        const long long row = p->kernel == VG_CONVECTION ? 2LL * p->N : p->N + 1;
+        const long long pitch = p->kernel == VG_CONVECTION ? row : p->tab_pitch;
         for (long long i = 0; i < n; ++i) {
+            const long long src = (i / row) * pitch + i % row;
             double re = 0, im = 0;
             if (p->fp64) {
                 const double* q = reinterpret_cast<const double*>(h.data());
-                re = p->table_complex ? q[2 * i] : q[i];
-                im = p->table_complex ? q[2 * i + 1] : 0.0;
+                re = p->table_complex ? q[2 * src] : q[src];
+                im = p->table_complex ? q[2 * src + 1] : 0.0;
             } else {
                 const float* q = reinterpret_cast<const float*>(h.data());
-                re = p->table_complex ? q[2 * i] : q[i];
-                im = p->table_complex ? q[2 * i + 1] : 0.0;
+                re = p->table_complex ? q[2 * src] : q[src];
+                im = p->table_complex ? q[2 * src + 1] : 0.0;
             }
             host_out[2 * i] = re * sc;
             host_out[2 * i + 1] = im * sc;

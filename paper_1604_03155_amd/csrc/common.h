@@ -82,6 +82,14 @@ struct PassDesc {
     // indices come from its column: d == 3: c = k2 * (2N) + k3; d == 2: c = k2.
     int d;
     int tabN;               // N of the plan (octant is (N+1)^d)
+    // 3D octant tables: entries between consecutive (k1, k2) rows, N + 1
+    // rounded up to a multiple of 16 so that runs of 16 entries starting at
+    // k3 = 16 m are whole 128-byte lines (complex64); 2D tables: N + 1
+    int tab_pitch;
+    // staged table fetch (3D, 2N = 512, FP32): element offset in `table` of
+    // the boundary block, which repeats the entries k3 = 16 (b + 1),
+    // b < N / 16, of every row in the order [k2][b][k1]; 0 when absent
+    unsigned tab_bnd;
     int table_complex;      // 0: real table (Laplace), 1: complex
     // spectral derivative along this pass's axis (gradient kinds): i*kappa,
     // kappa = kscale * signed(k), zero at the Nyquist index k = Laxis/2.
@@ -159,8 +167,12 @@ hipError_t launch_greens_contract(const GreensParams& g, int M2, int n_out, cons
                                   c64* out, hipStream_t s);
 hipError_t launch_cos_contract(const c64* in, c64* out, const double* cmat, long long O, int Min,
                                int Nout, long long I, hipStream_t s);
-hipError_t launch_round_table(const c64* in, void* out, long long n, int to_fp32, int complex_out,
-                              hipStream_t s);
+// FP64 octant (rows of N1 entries, dense) -> the kernel table: rows at pitch
+// `pitch`, rounded to FP32 (to_fp32) and kept complex or real; with nb > 0
+// (3D), entries k3 = 16 (b + 1), b < nb, are also written to the boundary
+// block at element offset bnd, index (k2 nb + b) N1 + k1.
+hipError_t launch_round_table(const c64* in, void* out, long long rows, int N1, int pitch, int to_fp32,
+                              int complex_out, long long bnd, int nb, hipStream_t s);
 // First contraction on the full lattice (g.full): rows = M^(d-1), K = M.
 hipError_t launch_greens_contract_full(const GreensParams& g, int n_out, const double* cmat, c64* out,
                                        hipStream_t s);

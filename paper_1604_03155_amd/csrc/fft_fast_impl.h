@@ -474,8 +474,8 @@ __device__ __forceinline__ void store_global(const cplx<R>* v, cplx<R>* __restri
 // FULL: the table holds every spectral index (convection kernel): flat =
 // e L^(d-1) + c.
 template <typename R, int L, int C, int NT, int MODE, RP P, int D, bool CPLX, bool HALF = false, bool FULL = false>
-__device__ __forceinline__ void table_fetch(cplx<R>* kt, const void* __restrict__ table, int tabN, int col0,
-                                            int nvalid, int t) {
+__device__ __forceinline__ void table_fetch(cplx<R>* kt, const void* __restrict__ table, int tabN, int tp,
+                                            int col0, int nvalid, int t) {
     constexpr int RAD = P.r[P.n - 1];
     constexpr int E = C * L / NT;
     if constexpr (FULL) {
@@ -495,7 +495,8 @@ __device__ __forceinline__ void table_fetch(cplx<R>* kt, const void* __restrict_
     }
     const int N1 = tabN + 1;
     // block strides as opaque scalars: per element one add, no multiply
-    const unsigned plane = uniform_u32((D == 3) ? (unsigned)(N1 * N1) : (unsigned)N1);
+    // (3D rows at pitch tp)
+    const unsigned plane = uniform_u32((D == 3) ? (unsigned)(N1 * tp) : (unsigned)N1);
     constexpr int LR = L / RAD;
     const unsigned step = uniform_u32((unsigned)LR * plane);
 #pragma unroll
@@ -506,10 +507,10 @@ __device__ __forceinline__ void table_fetch(cplx<R>* kt, const void* __restrict_
         unsigned rowoff;
         if constexpr (D == 3 && HALF) {
             const int k2 = col / N1, k3 = col - (col / N1) * N1;
-            rowoff = (unsigned)(min(k2, L - k2) * N1 + k3);
+            rowoff = (unsigned)(min(k2, L - k2) * tp + k3);
         } else if constexpr (D == 3) {
             const int k2 = col / L, k3 = col % L;
-            rowoff = (unsigned)(min(k2, L - k2) * N1 + min(k3, L - k3));
+            rowoff = (unsigned)(min(k2, L - k2) * tp + min(k3, L - k3));
         } else if constexpr (HALF) {
             rowoff = (unsigned)col;
         } else {
@@ -531,6 +532,81 @@ __device__ __forceinline__ void table_fetch(cplx<R>* kt, const void* __restrict_
             } else {
                 kt[i * RAD + r] = mk(ld_off<R>(table, flat * (unsigned)sizeof(R)), R(0));
             }
+        }
+    }
+}
+
+// Staged Khat fetch (3D fused column passes over the octant table, tiles of
+// C = 16 adjacent columns k3 = k3_0 + q of one spectral row k2, k3_0 a
+// multiple of 16).  The tile needs, for every k1 = 0 .. L/2, 16 consecutive
+// octant entries: k3' = k3_0 .. k3_0 + 15, or, for mirrored columns
+// (k3_0 >= L/2), k3' = L - k3_0 - 15 .. L - k3_0.  With the row pitch a
+// multiple of 16 the first run is one 128-byte line; of the second, the
+// first 15 entries are one line and the last (k3' = L - k3_0, a multiple of
+// 16) comes from the boundary block, where the entries of consecutive k1 are
+// adjacent.  Every entry is loaded once, at the start of the tile (lane c of
+// each group of 16 takes run position c), and goes to LDS after the forward
+// transform, where each thread picks the values of its spectral indices.
+template <int L, int C, int NT>
+struct TabStage {
+    static_assert(C == 16 && NT % C == 0, "tiles of 16 columns");
+    static constexpr int ROWS = L / 2 + 1;
+    static constexpr int N = ROWS * C;
+    static constexpr int PER = (N + NT - 1) / NT;
+};
+
+template <typename R, int L, int C, int NT, bool CPLX>
+__device__ __forceinline__ void tab_stage_issue(cplx<R>* tb, const PassDesc& p, int col0, int t) {
+    using TS = TabStage<L, C, NT>;
+    constexpr unsigned ES = CPLX ? sizeof(cplx<R>) : sizeof(R);
+    const unsigned N1 = (unsigned)p.tabN + 1u, tp = (unsigned)p.tab_pitch, nb = (unsigned)p.tabN / 16u;
+    const int k2 = col0 / L, k3 = col0 % L;
+    const unsigned k2f = (unsigned)min(k2, L - k2);
+    const bool mir = k3 >= L / 2;
+    const int c = t % C;
+    const unsigned row0 = (unsigned)(t / C);
+    // entry offset of row k1 = row0 + m NT / C: base + m * stride
+    unsigned base, stride;
+    if (mir && c == C - 1) {
+        base = p.tab_bnd + (k2f * nb + (unsigned)(L - k3) / 16u - 1u) * N1 + row0;
+        stride = NT / C;
+    } else {
+        base = row0 * N1 * tp + k2f * tp + (unsigned)(mir ? L - k3 - (C - 1) : k3) + (unsigned)c;
+        stride = (NT / C) * N1 * tp;
+    }
+#pragma unroll
+    for (int m = 0; m < TS::PER; ++m) {
+        if (m + 1 < TS::PER || t + m * NT < TS::N) {
+            const unsigned off = (base + (unsigned)m * stride) * ES;
+            if constexpr (CPLX) tb[m] = ld_off<cplx<R>>(p.table, off);
+            else tb[m] = mk(ld_off<R>(p.table, off), R(0));
+        }
+    }
+}
+
+template <typename R, int L, int C, int NT, RP P>
+__device__ __forceinline__ void tab_stage_read(const cplx<R>* tb, cplx<R>* kt, cplx<R>* lds, int col0, int t) {
+    using TS = TabStage<L, C, NT>;
+    constexpr int RAD = P.r[P.n - 1];
+    constexpr int E = C * L / NT;
+    constexpr int LR = L / RAD;
+    const bool mir = (col0 % L) >= L / 2;
+    const int c = t % C;
+    const int q0 = mir ? C - 1 - c : c;
+#pragma unroll
+    for (int m = 0; m < TS::PER; ++m) {
+        const int idx = t + m * NT;
+        if (m + 1 < TS::PER || idx < TS::N) lds[(idx / C) * C + q0] = tb[m];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < E / RAD; ++i) {
+        int q, j;
+        bmap<L, C, NT, MODE_COL, RAD>(t, i, q, j);
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) {
+            const int e = j + r * LR;
+            kt[i * RAD + r] = lds[min(e, L - e) * C + q];
         }
     }
 }
@@ -833,7 +909,12 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
     constexpr int NIN = (FL && FSB != 2) ? L / 2 : L;
     using LY = Lay<L, C, MODE, (int)sizeof(cplx<R>), use_split<R, L, MODE, FK, FS>() ? 65536 : kPadLimit>;
     constexpr int NLDS0 = use_split<R, L, MODE, FK, FS>() ? (LY::size + 1) / 2 : LY::size;
-    constexpr int NLDS = (FSB == 4 && C * (L + 1) > NLDS0) ? C * (L + 1) : NLDS0;
+    // staged Khat fetch: plain fused complex64 columns of length 512 (3D N = 256)
+    constexpr bool STG = FK == FK_FUSED && FSB == 0 && !HALF && !FULL && MODE == MODE_COL && D == 3 &&
+                         sizeof(R) == 4 && L == 512 && C == 16;
+    constexpr int NLDS1 = (FSB == 4 && C * (L + 1) > NLDS0) ? C * (L + 1) : NLDS0;
+    constexpr int NSTG = STG ? (L / 2 + 1) * C : 0;  // TabStage::N
+    constexpr int NLDS = NSTG > NLDS1 ? NSTG : NLDS1;
     __shared__ cplx<R> lds[NLDS];
     __shared__ cplx<R> twl[PO::twl ? L : 1];
     const cplx<R>* __restrict__ tw = reinterpret_cast<const cplx<R>*>(p.tw);
@@ -855,11 +936,27 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
     } else {
         cplx<R> vn[LoadSet<R, L, C, NT, PL, NIN>::NV];
         issue_loads<R, L, C, NT, MODE, PL, NIN>(vn, gin, tl, p.in_se, t);
+        if constexpr (STG) {
+            // the tile's table entries wait in tb until the forward transform
+            // is done (the dispatcher checks that the table has the boundary block)
+            constexpr bool SP = use_split<R, L, MODE, FK, FS>();
+            cplx<R> tb[TabStage<L, C, NT>::PER];
+            tab_stage_issue<R, L, C, NT, CPLX>(tb, p, tl.col0, t);
+            expand<R, L, C, NT, PL, NIN>(v, vn);
+            run_from<R, L, C, NT, MODE, -1, F, 0, SP>(v, lds, t, tw);
+            tab_stage_read<R, L, C, NT, F>(tb, kt, lds, tl.col0, t);
+            table_apply<R, E, CPLX>(v, kt);
+            __syncthreads();  // the inverse's first exchange overwrites the staged entries
+            run_from<R, L, C, NT, MODE, +1, I, 0, SP>(v, lds, t, tw);
+            store_global<R, L, C, NT, MODE, I, L / 2>(v, reinterpret_cast<cplx<R>*>(p.out), tl, p.out_se, t);
+            return;
+        }
         if constexpr (TAB && FSB == 2)
             table_fetch_fs<R, L, C, NT, MODE, F, CPLX, HALF, FULL>(kt, p.table, p.tabN, tl.col0, tl.nvalid, tl.o,
                                                                    p.fs_L1, p.L_big, t);
         else if constexpr (TAB)
-            table_fetch<R, L, C, NT, MODE, F, D, CPLX, HALF, FULL>(kt, p.table, p.tabN, tl.col0, tl.nvalid, t);
+            table_fetch<R, L, C, NT, MODE, F, D, CPLX, HALF, FULL>(kt, p.table, p.tabN, p.tab_pitch, tl.col0,
+                                                                tl.nvalid, t);
         expand<R, L, C, NT, PL, NIN>(v, vn);
     }
     tile_body<R, L, C, NT, MODE, FK, D, CPLX, FS>(v, kt, lds, tl, p, t, tw);
@@ -983,6 +1080,9 @@ hipError_t launch_shape(const PassDesc& p, int kind, hipStream_t s, const GroupA
             if (p.d != 2 || p.post_tw != 2) return hipErrorInvalidValue;
             return p.table_complex ? by_kind(I2{}, T_{}, I2{}) : by_kind(I2{}, F_{}, I2{});
         }
+        // the staged fetch of plain fused passes needs the table's boundary block
+        if (sizeof(R) == 4 && L == 512 && C == 16 && p.d == 3 && kind == KIND_FUSED && !p.tab_bnd)
+            return hipErrorInvalidValue;
         if (p.d == 3) return p.table_complex ? by_kind(I3{}, T_{}, I0{}) : by_kind(I3{}, F_{}, I0{});
         return p.table_complex ? by_kind(I2{}, T_{}, I0{}) : by_kind(I2{}, F_{}, I0{});
     }

@@ -99,7 +99,7 @@ __device__ __forceinline__ cplx<R> table_value(const PassDesc& p, int e, int col
     long long flat;
     if (p.d == 3) {
         const int k2 = col / L, k3 = col - (col / L) * L;
-        flat = ((long long)f1 * N1 + min(k2, L - k2)) * N1 + min(k3, L - k3);
+        flat = ((long long)f1 * N1 + min(k2, L - k2)) * p.tab_pitch + min(k3, L - k3);
     } else {
         flat = (long long)f1 * N1 + min(col, L - col);
     }

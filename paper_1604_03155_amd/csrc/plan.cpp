@@ -311,8 +311,12 @@ vg_status precompute_full(vg_plan* p, hipStream_t s, bool keep_T) {
     p->table_complex = 1;
     const size_t esz = p->fp64 ? 16 : 8;
     p->table_bytes = (size_t)nK * esz;
+    p->table_alg_bytes = p->table_bytes;
+    p->tab_pitch = (int)L;
+    p->tab_bnd = 0;
     if ((he = dev_malloc(&p->table, p->table_bytes)) != hipSuccess) return chk(he, "kernel table");
-    if ((he = launch_round_table(K.as<c64>(), p->table, nK, p->fp64 ? 0 : 1, 1, s)) != hipSuccess)
+    if ((he = launch_round_table(K.as<c64>(), p->table, nK / L, (int)L, (int)L, p->fp64 ? 0 : 1, 1, 0, 0, s)) !=
+        hipSuccess)
         return chk(he, "table rounding");
     (void)hipEventRecord(e1, s);
     if ((he = hipStreamSynchronize(s)) != hipSuccess) return chk(he, "precompute");
@@ -395,9 +399,18 @@ vg_status precompute(vg_plan* p, hipStream_t s, bool keep_T) {
     for (int i = 0; i < d; ++i) nK *= N1;
     p->table_complex = (p->kernel == VG_HELMHOLTZ || p->kernel == VG_LAPLACE_HELMHOLTZ) ? 1 : 0;
     const size_t esz = (p->fp64 ? 8 : 4) * (p->table_complex ? 2 : 1);
-    p->table_bytes = (size_t)nK * esz;
+    // 3D rows padded to 16 entries; the FP32 tables of 2N = 512 also carry
+    // the boundary block of the staged fetch in the fused pass
+    const long long rows = nK / N1;
+    p->tab_pitch = d == 3 ? (int)((N1 + 15) / 16 * 16) : (int)N1;
+    const long long nPad = rows * p->tab_pitch;
+    const int nb = (d == 3 && !p->fp64 && 2 * N == 512) ? N / 16 : 0;
+    p->tab_bnd = nb ? (unsigned)nPad : 0u;
+    p->table_alg_bytes = (size_t)nK * esz;
+    p->table_bytes = (size_t)(nPad + (long long)nb * N1 * N1) * esz;
     if ((he = dev_malloc(&p->table, p->table_bytes)) != hipSuccess) return chk(he, "kernel table");
-    if ((he = launch_round_table(K.as<c64>(), p->table, nK, p->fp64 ? 0 : 1, p->table_complex, s)) != hipSuccess)
+    if ((he = launch_round_table(K.as<c64>(), p->table, rows, (int)N1, p->tab_pitch, p->fp64 ? 0 : 1,
+                                 p->table_complex, nPad, nb, s)) != hipSuccess)
         return chk(he, "table rounding");
     (void)hipEventRecord(e1, s);
     if ((he = hipStreamSynchronize(s)) != hipSuccess) return chk(he, "precompute");
@@ -840,7 +853,7 @@ double pass_bytes(const vg_plan* p, const PassStep& s) {
     const double pencils = (s.mode == MODE_COL) ? (double)s.desc.outer * s.desc.inner : (double)s.desc.outer;
     double outs = (s.out2_buf != BUF_NONE) ? 2.0 : 1.0;
     double b = pencils * es * (s.desc.n_in + outs * s.desc.n_out);
-    if (s.kind == KIND_FUSED || s.kind == KIND_FUSED_GRAD || s.kind == KIND_FUSED_DERIV) b += (double)p->table_bytes;
+    if (s.kind == KIND_FUSED || s.kind == KIND_FUSED_GRAD || s.kind == KIND_FUSED_DERIV) b += (double)p->table_alg_bytes;
     return b;
 }
 }  // namespace
@@ -866,6 +879,8 @@ BoundStep bind_step(const vg_plan* p, const Program& prog, const PassStep& st, c
     BoundStep b;
     b.desc = st.desc;
     b.desc.table = p->table;  // programs are built before the precompute fills the table
+    b.desc.tab_pitch = p->tab_pitch;
+    b.desc.tab_bnd = p->tab_bnd;
     b.desc.in = resolve(st.in_buf);
     b.desc.out = resolve(st.out_buf);
     b.desc.out2 = resolve(st.out2_buf);

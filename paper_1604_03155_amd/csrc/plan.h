@@ -66,7 +66,10 @@ struct vg_plan {
     std::vector<int> radices;     // Stockham radix plan of length 2N
     std::map<int, void*> twiddles; // device twiddle tables e^{-2 pi i t / L} per length L
     void* table = nullptr;        // device, (N+1)^d Khat octant / (2N)^d
-    size_t table_bytes = 0;
+    size_t table_bytes = 0;       // allocated bytes (padding and boundary block included)
+    size_t table_alg_bytes = 0;   // bytes of the octant itself, (N+1)^d entries (read once per fused pass)
+    int tab_pitch = 0;            // see PassDesc::tab_pitch
+    unsigned tab_bnd = 0;         // see PassDesc::tab_bnd
     int table_complex = 0;
     void* T_dev = nullptr;        // device, N^d complex128 (keep_operator)
     double precompute_ms = 0.0;

@@ -328,11 +328,7 @@ __global__ void combine_kernel(const c64* __restrict__ a, const c64* __restrict_
     out[i] = mk(x.x - sign * y.y, x.y + sign * y.x);
 }
 
-__global__ void round_table_kernel(const c64* __restrict__ in, void* __restrict__ out, long long n, int to_fp32,
-                                   int complex_out) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const c64 v = in[i];
+__device__ __forceinline__ void put_entry(void* out, long long i, c64 v, int to_fp32, int complex_out) {
     if (to_fp32) {
         if (complex_out) {
             reinterpret_cast<c32*>(out)[i] = mk((float)v.x, (float)v.y);
@@ -345,6 +341,22 @@ __global__ void round_table_kernel(const c64* __restrict__ in, void* __restrict_
         } else {
             reinterpret_cast<double*>(out)[i] = v.x;
         }
+    }
+}
+
+// One thread per padded table slot: row r, entry e < pitch (pads are zero).
+__global__ void round_table_kernel(const c64* __restrict__ in, void* __restrict__ out, long long rows, int N1,
+                                   int pitch, int to_fp32, int complex_out, long long bnd, int nb) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * pitch) return;
+    const long long r = i / pitch;
+    const int e = (int)(i - r * pitch);
+    const c64 v = e < N1 ? in[r * N1 + e] : mk(0.0, 0.0);
+    put_entry(out, i, v, to_fp32, complex_out);
+    if (nb > 0 && e >= 16 && (e & 15) == 0 && (e >> 4) <= nb) {
+        // r = k1 N1 + k2 (3D octant rows)
+        const long long k1 = r / N1, k2 = r - (r / N1) * N1;
+        put_entry(out, bnd + (k2 * nb + ((e >> 4) - 1)) * N1 + k1, v, to_fp32, complex_out);
     }
 }
 
@@ -385,10 +397,14 @@ hipError_t launch_cos_contract(const c64* in, c64* out, const double* cmat, long
     return hipGetLastError();
 }
 
-hipError_t launch_round_table(const c64* in, void* out, long long n, int to_fp32, int complex_out,
-                              hipStream_t s) {
+hipError_t launch_round_table(const c64* in, void* out, long long rows, int N1, int pitch, int to_fp32,
+                              int complex_out, long long bnd, int nb, hipStream_t s) {
+    if (pitch < N1 || (nb > 0 && (N1 - 1) < 16 * nb)) return hipErrorInvalidValue;
+    const long long n = rows * pitch;
+    if (n <= 0) return hipSuccess;
     const unsigned blocks = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(round_table_kernel, dim3(blocks), dim3(256), 0, s, in, out, n, to_fp32, complex_out);
+    hipLaunchKernelGGL(round_table_kernel, dim3(blocks), dim3(256), 0, s, in, out, rows, N1, pitch, to_fp32,
+                       complex_out, bnd, nb);
     return hipGetLastError();
 }
 
