@@ -83,12 +83,14 @@ struct PassDesc {
     int d;
     int tabN;               // N of the plan (octant is (N+1)^d)
     // 3D octant tables: entries between consecutive (k1, k2) rows, N + 1
-    // rounded up to a multiple of 16 so that runs of 16 entries starting at
-    // k3 = 16 m are whole 128-byte lines (complex64); 2D tables: N + 1
+    // rounded up to a multiple of 16 (N >= 96) so that runs of 16 entries
+    // starting at k3 = 16 m are whole 128-byte lines (complex64); 2D tables
+    // and 3D N < 96: N + 1
     int tab_pitch;
-    // staged table fetch (3D, 2N = 512, FP32): element offset in `table` of
-    // the boundary block, which repeats the entries k3 = 16 (b + 1),
-    // b < N / 16, of every row in the order [k2][b][k1]; 0 when absent
+    // staged table fetch (3D FP32, staged_fetch_length(2N)): element offset
+    // in `table` of the boundary block, which repeats the entries
+    // k3 = 16 (b + 1), b < N / 16, of every row in the order [k2][b][k1];
+    // 0 when absent
     unsigned tab_bnd;
     int table_complex;      // 0: real table (Laplace), 1: complex
     // spectral derivative along this pass's axis (gradient kinds): i*kappa,
@@ -121,6 +123,12 @@ struct PassDesc {
     // pass, so that they cover whole lines
     int stream;
 };
+
+// Fused 3D column passes whose complex64 kernel stages the Khat tile through
+// LDS (tiles of 16 columns); their plans' FP32 tables carry the boundary
+// block (PassDesc::tab_bnd).  Measured faster at 2N = 192, 256 and 512; at
+// 2N = 96 and 128 the table is L2-resident and the staging gains nothing.
+__host__ __device__ constexpr bool staged_fetch_length(int L) { return L == 192 || L == 256 || L == 512; }
 
 // ----------------------------------------------------- plan precompute ----
 struct GreensParams {

@@ -538,7 +538,7 @@ __device__ __forceinline__ void table_fetch(cplx<R>* kt, const void* __restrict_
 
 // Staged Khat fetch (3D fused column passes over the octant table, tiles of
 // C = 16 adjacent columns k3 = k3_0 + q of one spectral row k2, k3_0 a
-// multiple of 16).  The tile needs, for every k1 = 0 .. L/2, 16 consecutive
+// multiple of 16, N a multiple of 16).  The tile needs, for every k1 = 0 .. L/2, 16 consecutive
 // octant entries: k3' = k3_0 .. k3_0 + 15, or, for mirrored columns
 // (k3_0 >= L/2), k3' = L - k3_0 - 15 .. L - k3_0.  With the row pitch a
 // multiple of 16 the first run is one 128-byte line; of the second, the
@@ -909,9 +909,9 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
     constexpr int NIN = (FL && FSB != 2) ? L / 2 : L;
     using LY = Lay<L, C, MODE, (int)sizeof(cplx<R>), use_split<R, L, MODE, FK, FS>() ? 65536 : kPadLimit>;
     constexpr int NLDS0 = use_split<R, L, MODE, FK, FS>() ? (LY::size + 1) / 2 : LY::size;
-    // staged Khat fetch: plain fused complex64 columns of length 512 (3D N = 256)
+    // staged Khat fetch: plain fused complex64 columns of the staged lengths
     constexpr bool STG = FK == FK_FUSED && FSB == 0 && !HALF && !FULL && MODE == MODE_COL && D == 3 &&
-                         sizeof(R) == 4 && L == 512 && C == 16;
+                         sizeof(R) == 4 && staged_fetch_length(L) && C == 16;
     constexpr int NLDS1 = (FSB == 4 && C * (L + 1) > NLDS0) ? C * (L + 1) : NLDS0;
     constexpr int NSTG = STG ? (L / 2 + 1) * C : 0;  // TabStage::N
     constexpr int NLDS = NSTG > NLDS1 ? NSTG : NLDS1;
@@ -1081,7 +1081,7 @@ hipError_t launch_shape(const PassDesc& p, int kind, hipStream_t s, const GroupA
             return p.table_complex ? by_kind(I2{}, T_{}, I2{}) : by_kind(I2{}, F_{}, I2{});
         }
         // the staged fetch of plain fused passes needs the table's boundary block
-        if (sizeof(R) == 4 && L == 512 && C == 16 && p.d == 3 && kind == KIND_FUSED && !p.tab_bnd)
+        if (sizeof(R) == 4 && staged_fetch_length(L) && C == 16 && p.d == 3 && kind == KIND_FUSED && !p.tab_bnd)
             return hipErrorInvalidValue;
         if (p.d == 3) return p.table_complex ? by_kind(I3{}, T_{}, I0{}) : by_kind(I3{}, F_{}, I0{});
         return p.table_complex ? by_kind(I2{}, T_{}, I0{}) : by_kind(I2{}, F_{}, I0{});

@@ -399,12 +399,13 @@ vg_status precompute(vg_plan* p, hipStream_t s, bool keep_T) {
     for (int i = 0; i < d; ++i) nK *= N1;
     p->table_complex = (p->kernel == VG_HELMHOLTZ || p->kernel == VG_LAPLACE_HELMHOLTZ) ? 1 : 0;
     const size_t esz = (p->fp64 ? 8 : 4) * (p->table_complex ? 2 : 1);
-    // 3D rows padded to 16 entries; the FP32 tables of 2N = 512 also carry
-    // the boundary block of the staged fetch in the fused pass
+    // 3D rows padded to 16 entries from N = 96 on (below, the table is
+    // L2-resident, and its reads from HBM grow with the padding); the FP32
+    // tables of the staged lengths also carry the boundary block
     const long long rows = nK / N1;
-    p->tab_pitch = d == 3 ? (int)((N1 + 15) / 16 * 16) : (int)N1;
+    p->tab_pitch = (d == 3 && N >= 96) ? (int)((N1 + 15) / 16 * 16) : (int)N1;
     const long long nPad = rows * p->tab_pitch;
-    const int nb = (d == 3 && !p->fp64 && 2 * N == 512) ? N / 16 : 0;
+    const int nb = (d == 3 && !p->fp64 && N % 16 == 0 && staged_fetch_length(2 * N)) ? N / 16 : 0;
     p->tab_bnd = nb ? (unsigned)nPad : 0u;
     p->table_alg_bytes = (size_t)nK * esz;
     p->table_bytes = (size_t)(nPad + (long long)nb * N1 * N1) * esz;

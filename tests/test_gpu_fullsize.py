@@ -9,7 +9,8 @@ stream), against the FP64 oracle on the whole grid:
     e^{i a.x}, |a| <= 10): FP32 potential at 1e-5 and FP64 at 1e-12; at
     N = 256 also the FP32 gradient at 1e-5;
   * the same N = 256 plan applied twice in a row to different densities
-    (workspace reuse) and to the density in place.
+    (workspace reuse) and to the density in place;
+  * 3D N = 256 FP32 with the real tables (Laplace, biharmonic) on white noise.
 
 The 2D N = 4096, batched and N = 512 configurations are held to the oracle or
 closed forms in test_gpu_parity.py, test_gpu_batched.py and
@@ -72,6 +73,26 @@ def test_laplace3d_n32_fp64_oracle_and_closed_form():
     # 2.5e-5 from the closed form (the oracle's own distance): the method's
     # error at this resolution, not a kernel error
     assert e <= 5e-5
+
+
+@pytest.mark.parametrize("kernel", ["laplace", "biharmonic"])
+def test_real_table_n256_fp32(kernel):
+    """3D N = 256 FP32 with a real Khat table (the staged fetch's real-valued
+    variant, padded table and boundary block) against the oracle on the
+    whole grid, white-noise density."""
+    say("real table n256", kernel)
+    import torch
+
+    import paper_1604_03155_amd as vg
+    from oracle import operator as op
+    N = 256
+    rng = np.random.default_rng(2560)
+    f = rng.standard_normal((N,) * 3) + 1j * rng.standard_normal((N,) * 3)
+    ref = op.Plan(3, N, kernel).apply(f)
+    p = vg.Plan(3, N, kernel, precision="fp32")
+    out = p.apply(torch.from_numpy(f.astype(np.complex64)).cuda())
+    torch.cuda.synchronize()
+    check(out.cpu().numpy(), ref, FP32_TOL, f"{kernel} fp32 apply")
 
 
 @pytest.mark.parametrize("name", ["helmholtz3d_k20_n128", "helmholtz3d_k20_n256"])

@@ -95,6 +95,8 @@ APPLY_CASES = [
     (2, 48, "helmholtz", 21.0), (2, 96, "laplace", 0.0), (2, 128, "helmholtz", 75.0), (2, 512, "laplace", 0.0),
     (3, 16, "biharmonic", 0.0), (3, 32, "laplace_helmholtz", 10.0), (3, 48, "biharmonic", 0.0),
     (2, 30, "laplace_helmholtz", 20.0), (2, 64, "biharmonic", 0.0), (2, 256, "laplace_helmholtz", 50.0),
+    # the staged table fetch of the fused pass (2N = 192, 256) with real and complex tables
+    (3, 96, "laplace", 0.0), (3, 128, "biharmonic", 0.0), (3, 128, "laplace_helmholtz", 25.0),
 ]
 
 
