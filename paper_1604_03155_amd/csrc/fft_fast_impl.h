@@ -132,6 +132,27 @@ struct Lay {
     }
 };
 
+// Column tiles of two-stage plans in the plain fused kernels (CPAD): C
+// padding slots after every block of RAD0 = P.r[0] elements.  The
+// first-stage writes (element j RAD0 + r of lane j) then fall in distinct
+// banks, and the pad index is e / RAD0 = j on write and r on read
+// (e = j + r RAD0), per lane or compile-time.  Measured on the fused pass:
+// 3D N = 256 -1.6%, N = 512 -0.6%; the gradient kinds of length 1024 were
+// slower with it (fused derivative 3.29 -> 3.79 ms), the unfused column
+// passes unchanged, so only the plain fused kind uses it.
+template <int L, int C, int MODE, RP P, bool CPAD>
+struct ColPad {
+    static constexpr bool on = CPAD && MODE == MODE_COL && P.n == 2;
+    __device__ static __forceinline__ int add(int e) { return on ? (e / P.r[0]) * C : 0; }
+};
+// slots a two-stage column tile needs, padding for either plan's first radix
+template <int L, int C, RP F>
+constexpr int col_pad_slots() {
+    if (F.n != 2) return 0;
+    const int r = F.r[0] < F.r[1] ? F.r[0] : F.r[1];
+    return C * (L / r);
+}
+
 template <int L, int C, int NT, int MODE, int RAD>
 __device__ __forceinline__ void bmap(int t, int i, int& q, int& j) {
     constexpr int LR = L / RAD;
@@ -235,9 +256,10 @@ __device__ __forceinline__ void compute_stage(cplx<R>* v, int t, const cplx<R>* 
 // conflicts (2D N = 4096 forward rows 0.122 -> 0.115 ms).
 constexpr int kPadLimit = 81920;
 
-template <typename R, int L, int C, int NT, int MODE, RP P, int s, bool SPLIT>
+template <typename R, int L, int C, int NT, int MODE, RP P, int s, bool SPLIT, bool CPAD = false>
 __device__ __forceinline__ void exchange(cplx<R>* v, cplx<R>* lds, int t) {
     using LY = Lay<L, C, MODE, (int)sizeof(cplx<R>), SPLIT ? 65536 : kPadLimit>;
+    using CP = ColPad<L, C, MODE, P, CPAD>;
     constexpr int RAD = P.r[s];
     constexpr int NS = ns_before(P, s);
     constexpr int E = C * L / NT;
@@ -252,7 +274,10 @@ __device__ __forceinline__ void exchange(cplx<R>* v, cplx<R>* lds, int t) {
                 bmap<L, C, NT, MODE, RAD>(t, i, q, j);
                 const int ob = (j / NS) * NS * RAD + (j % NS);
 #pragma unroll
-                for (int r = 0; r < RAD; ++r) lr[LY::idx(q, ob + r * NS)] = part ? v[i * RAD + r].y : v[i * RAD + r].x;
+                for (int r = 0; r < RAD; ++r) {
+                    const int e = ob + r * NS;
+                    lr[LY::idx(q, e) + CP::add(e)] = part ? v[i * RAD + r].y : v[i * RAD + r].x;
+                }
             }
             __syncthreads();
 #pragma unroll
@@ -261,7 +286,8 @@ __device__ __forceinline__ void exchange(cplx<R>* v, cplx<R>* lds, int t) {
                 bmap<L, C, NT, MODE, RN>(t, i, q, j);
 #pragma unroll
                 for (int r = 0; r < RN; ++r) {
-                    const R x = lr[LY::idx(q, j + r * (L / RN))];
+                    const int e = j + r * (L / RN);
+                    const R x = lr[LY::idx(q, e) + CP::add(e)];
                     if (part) v[i * RN + r].y = x;
                     else v[i * RN + r].x = x;
                 }
@@ -275,7 +301,10 @@ __device__ __forceinline__ void exchange(cplx<R>* v, cplx<R>* lds, int t) {
             bmap<L, C, NT, MODE, RAD>(t, i, q, j);
             const int ob = (j / NS) * NS * RAD + (j % NS);
 #pragma unroll
-            for (int r = 0; r < RAD; ++r) lds[LY::idx(q, ob + r * NS)] = v[i * RAD + r];
+            for (int r = 0; r < RAD; ++r) {
+                const int e = ob + r * NS;
+                lds[LY::idx(q, e) + CP::add(e)] = v[i * RAD + r];
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -283,18 +312,21 @@ __device__ __forceinline__ void exchange(cplx<R>* v, cplx<R>* lds, int t) {
             int q, j;
             bmap<L, C, NT, MODE, RN>(t, i, q, j);
 #pragma unroll
-            for (int r = 0; r < RN; ++r) v[i * RN + r] = lds[LY::idx(q, j + r * (L / RN))];
+            for (int r = 0; r < RN; ++r) {
+                const int e = j + r * (L / RN);
+                v[i * RN + r] = lds[LY::idx(q, e) + CP::add(e)];
+            }
         }
         __syncthreads();
     }
 }
 
-template <typename R, int L, int C, int NT, int MODE, int DIR, RP P, int s, bool SPLIT = false>
+template <typename R, int L, int C, int NT, int MODE, int DIR, RP P, int s, bool SPLIT = false, bool CPAD = false>
 __device__ __forceinline__ void run_from(cplx<R>* v, cplx<R>* lds, int t, const cplx<R>* __restrict__ tw) {
     compute_stage<R, L, C, NT, MODE, DIR, P, s>(v, t, tw);
     if constexpr (s + 1 < P.n) {
-        exchange<R, L, C, NT, MODE, P, s, SPLIT>(v, lds, t);
-        run_from<R, L, C, NT, MODE, DIR, P, s + 1, SPLIT>(v, lds, t, tw);
+        exchange<R, L, C, NT, MODE, P, s, SPLIT, CPAD>(v, lds, t);
+        run_from<R, L, C, NT, MODE, DIR, P, s + 1, SPLIT, CPAD>(v, lds, t, tw);
     }
 }
 
@@ -872,14 +904,16 @@ __device__ __forceinline__ void tile_body(cplx<R>* v, cplx<R>* kt, cplx<R>* lds,
         run_from<R, L, C, NT, MODE, +1, I, 0, SP>(w, lds, t, tw);
         store_global<R, L, C, NT, MODE, I, L / 2>(w, gout2, tl, p.out_se, t);
     } else {
-        run_from<R, L, C, NT, MODE, -1, F, 0, SP>(v, lds, t, tw);
+        // exchange padding (ColPad) in the plain fused kind only
+        constexpr bool CPD = FK == FK_FUSED && FS == 0;
+        run_from<R, L, C, NT, MODE, -1, F, 0, SP, CPD>(v, lds, t, tw);
         table_apply<R, E, CPLX>(v, kt);
         if constexpr (FK == FK_FUSED_DERIV) {
             if constexpr (FSB == 2) deriv_copy<R, L, C, NT, MODE, F.r[F.n - 1]>(v, v, ks, t, tl.o, p.fs_L1, p.L_big);
             else deriv_copy<R, L, C, NT, MODE, F.r[F.n - 1]>(v, v, ks, t);
         }
         if constexpr (FK == FK_FUSED || FK == FK_FUSED_DERIV) {
-            run_from<R, L, C, NT, MODE, +1, I, 0, SP>(v, lds, t, tw);
+            run_from<R, L, C, NT, MODE, +1, I, 0, SP, CPD>(v, lds, t, tw);
             store_global<R, L, C, NT, MODE, I, NOUTI, PTI>(v, gout, tl, p.out_se, t, p.tw_big);
         } else {
             cplx<R> w[E];
@@ -908,7 +942,8 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
     constexpr bool FULL = (FS & 16) != 0;
     constexpr int NIN = (FL && FSB != 2) ? L / 2 : L;
     using LY = Lay<L, C, MODE, (int)sizeof(cplx<R>), use_split<R, L, MODE, FK, FS>() ? 65536 : kPadLimit>;
-    constexpr int NLDS0 = use_split<R, L, MODE, FK, FS>() ? (LY::size + 1) / 2 : LY::size;
+    constexpr int LYP = LY::size + ((MODE == MODE_COL && FK == FK_FUSED && FS == 0) ? col_pad_slots<L, C, F>() : 0);
+    constexpr int NLDS0 = use_split<R, L, MODE, FK, FS>() ? (LYP + 1) / 2 : LYP;
     // staged Khat fetch: plain fused complex64 columns of the staged lengths
     constexpr bool STG = FK == FK_FUSED && FSB == 0 && !HALF && !FULL && MODE == MODE_COL && D == 3 &&
                          sizeof(R) == 4 && staged_fetch_length(L) && C == 16;
@@ -943,11 +978,11 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
             cplx<R> tb[TabStage<L, C, NT>::PER];
             tab_stage_issue<R, L, C, NT, CPLX>(tb, p, tl.col0, t);
             expand<R, L, C, NT, PL, NIN>(v, vn);
-            run_from<R, L, C, NT, MODE, -1, F, 0, SP>(v, lds, t, tw);
+            run_from<R, L, C, NT, MODE, -1, F, 0, SP, true>(v, lds, t, tw);
             tab_stage_read<R, L, C, NT, F>(tb, kt, lds, tl.col0, t);
             table_apply<R, E, CPLX>(v, kt);
             __syncthreads();  // the inverse's first exchange overwrites the staged entries
-            run_from<R, L, C, NT, MODE, +1, I, 0, SP>(v, lds, t, tw);
+            run_from<R, L, C, NT, MODE, +1, I, 0, SP, true>(v, lds, t, tw);
             store_global<R, L, C, NT, MODE, I, L / 2>(v, reinterpret_cast<cplx<R>*>(p.out), tl, p.out_se, t);
             return;
         }
