@@ -60,6 +60,8 @@ TABLE_CASES = [
     (2, 30, "helmholtz", 200.0), (2, 6, "laplace", 0.0),
     (3, 8, "biharmonic", 0.0), (3, 10, "laplace_helmholtz", 6.0), (2, 16, "biharmonic", 0.0),
     (2, 20, "laplace_helmholtz", 15.0), (2, 40, "biharmonic", 0.0),
+    # 3D N >= 96: rows stored at a padded pitch, unpadded by vg_plan_kernel_hat
+    (3, 96, "helmholtz", 20.0),
 ]
 
 
@@ -75,8 +77,10 @@ def test_plan_tables_fp64_match_oracle(d, N, kernel, k):
     assert np.max(np.abs(K - o.K_oct)) <= FP64_TOL * np.max(np.abs(o.K_oct))
 
 
-@pytest.mark.parametrize("d,N,kernel,k", [(3, 8, "helmholtz", 20.0), (2, 16, "laplace", 0.0)])
+@pytest.mark.parametrize("d,N,kernel,k", [(3, 8, "helmholtz", 20.0), (2, 16, "laplace", 0.0),
+                                          (3, 128, "laplace", 0.0), (3, 128, "helmholtz", 30.0)])
 def test_plan_table_fp32_rounded_once(d, N, kernel, k):
+    """FP32 tables, including padded 3D rows with the boundary block (N = 128)."""
     vg = _vg()
     p = vg.Plan(d, N, kernel, k, precision="fp32")
     o = oracle_plan(d, N, kernel, k)
