@@ -192,6 +192,7 @@ def test_linearity_on_gpu():
 
 
 @pytest.mark.parametrize("d,N,kernel,k", [(3, 32, "helmholtz", 9.0), (3, 48, "laplace", 0.0),
+                                          (3, 96, "helmholtz", 20.0),  # padded table rows
                                           (2, 128, "helmholtz", 30.0), (2, 512, "helmholtz", 60.0),
                                           (2, 1024, "helmholtz", 50.0)])
 def test_specialised_and_generic_passes_agree(d, N, kernel, k, monkeypatch):
