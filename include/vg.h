@@ -117,7 +117,10 @@ typedef struct vg_plan_info {
     double k, L;
     int P;
     double precompute_ms;     /* device time of the FP64 precompute (kernel spectrum -> T -> Khat) */
-    size_t table_bytes;       /* bytes of the Khat octant kept for applies */
+    size_t table_bytes;       /* device bytes of the kernel table kept for applies: the Khat octant
+                                 ((N+1)^d entries; 3D rows padded to 16 entries from N = 96 on;
+                                 FP32 3D N = 96, 128, 256 add a block repeating every 16th k3
+                                 entry) or, for the convection kernel, the full (2N)^d table */
     size_t workspace_bytes;   /* vg_workspace_size */
     size_t gradient_workspace_bytes;
     int tune;                 /* vg_tune_mode the plan was created with */

@@ -569,8 +569,8 @@ __device__ __forceinline__ void table_fetch(cplx<R>* kt, const void* __restrict_
 }
 
 // Staged Khat fetch (3D fused column passes over the octant table, tiles of
-// C = 16 adjacent columns k3 = k3_0 + q of one spectral row k2, k3_0 a
-// multiple of 16, N a multiple of 16).  The tile needs, for every k1 = 0 .. L/2, 16 consecutive
+// C = 16 adjacent columns k3 = k3_0 + q of one spectral row k2, k3_0 and N
+// multiples of 16).  The tile needs, for every k1 = 0 .. L/2, 16 consecutive
 // octant entries: k3' = k3_0 .. k3_0 + 15, or, for mirrored columns
 // (k3_0 >= L/2), k3' = L - k3_0 - 15 .. L - k3_0.  With the row pitch a
 // multiple of 16 the first run is one 128-byte line; of the second, the
