@@ -487,6 +487,15 @@ def main():
             cfg["helmholtz3d_k150_n512_phi_grad"] = large_gradient_config(vg, 5, 2)
             torch.cuda.empty_cache()
         result["configs"] = cfg
+    # the paper's own timing for the closest workload, as context (another
+    # machine and another workload, hence not vs_baseline)
+    result["paper_context"] = {
+        "source": "Section 5.3, Table 7: Lippmann-Schwinger solve of a smoothed cube, 3D N = 250 (500^3 padded)",
+        "seconds_per_matvec_upper_bound": 3.78,
+        "note": "solve time over matvec count; one matvec is one forward and one inverse padded FFT convolution",
+        "hardware": "two 8-core Intel Xeon E5-2450",
+        "precision": "not stated",
+    }
     print(json.dumps(result), flush=True)
 
 
