@@ -133,17 +133,19 @@ struct Lay {
 };
 
 // Column tiles of two-stage plans in the plain fused kernels (CPAD): C
-// padding slots after every block of RAD0 = P.r[0] elements.  The
-// first-stage writes (element j RAD0 + r of lane j) then fall in distinct
-// banks, and the pad index is e / RAD0 = j on write and r on read
-// (e = j + r RAD0), per lane or compile-time.  Measured on the fused pass:
+// padding slots after every block of RAD0 = P.r[0] elements, slot
+// e C + q + (e / RAD0) C.  The first-stage writes (element j RAD0 + r of
+// lane j) then fall in distinct banks.  The block index is j on write and r
+// on read (element j + r RAD0 with j < RAD0), so it is added as such: per
+// lane or compile-time.  Measured on the fused pass:
 // 3D N = 256 -1.6%, N = 512 -0.6%; the gradient kinds of length 1024 were
 // slower with it (fused derivative 3.29 -> 3.79 ms), the unfused column
 // passes unchanged, so only the plain fused kind uses it.
 template <int L, int C, int MODE, RP P, bool CPAD>
 struct ColPad {
     static constexpr bool on = CPAD && MODE == MODE_COL && P.n == 2;
-    __device__ static __forceinline__ int add(int e) { return on ? (e / P.r[0]) * C : 0; }
+    // pad slots before block b
+    __host__ __device__ static constexpr int add(int b) { return on ? b * C : 0; }
 };
 // slots a two-stage column tile needs, padding for either plan's first radix
 template <int L, int C, RP F>
@@ -264,6 +266,20 @@ __device__ __forceinline__ void exchange(cplx<R>* v, cplx<R>* lds, int t) {
     constexpr int NS = ns_before(P, s);
     constexpr int E = C * L / NT;
     constexpr int RN = P.r[s + 1];
+    static_assert(!CP::on || s == 0, "the padded layout covers the one exchange of a two-stage plan");
+    // Column slots are linear in the element (e C + q, plus the pad), so the
+    // writes of lane (q, j) sit at a lane base plus r NS C and the reads at a
+    // lane base plus r BS: immediate offsets, no per-element index
+    // arithmetic.  Row tiles keep LY::idx (padded every 16 elements).
+    constexpr int BS = (L / RN) * C + CP::add(1);
+    auto wslot = [&](int q, int j, int ob, int r) -> int {
+        if constexpr (MODE == MODE_COL) return (ob * C + q + CP::add(j)) + r * NS * C;
+        else return LY::idx(q, ob + r * NS);
+    };
+    auto rslot = [&](int q, int j, int r) -> int {
+        if constexpr (MODE == MODE_COL) return (j * C + q) + r * BS;
+        else return LY::idx(q, j + r * (L / RN));
+    };
     if constexpr (SPLIT) {
         R* lr = reinterpret_cast<R*>(lds);
 #pragma unroll
@@ -274,10 +290,7 @@ __device__ __forceinline__ void exchange(cplx<R>* v, cplx<R>* lds, int t) {
                 bmap<L, C, NT, MODE, RAD>(t, i, q, j);
                 const int ob = (j / NS) * NS * RAD + (j % NS);
 #pragma unroll
-                for (int r = 0; r < RAD; ++r) {
-                    const int e = ob + r * NS;
-                    lr[LY::idx(q, e) + CP::add(e)] = part ? v[i * RAD + r].y : v[i * RAD + r].x;
-                }
+                for (int r = 0; r < RAD; ++r) lr[wslot(q, j, ob, r)] = part ? v[i * RAD + r].y : v[i * RAD + r].x;
             }
             __syncthreads();
 #pragma unroll
@@ -286,8 +299,7 @@ __device__ __forceinline__ void exchange(cplx<R>* v, cplx<R>* lds, int t) {
                 bmap<L, C, NT, MODE, RN>(t, i, q, j);
 #pragma unroll
                 for (int r = 0; r < RN; ++r) {
-                    const int e = j + r * (L / RN);
-                    const R x = lr[LY::idx(q, e) + CP::add(e)];
+                    const R x = lr[rslot(q, j, r)];
                     if (part) v[i * RN + r].y = x;
                     else v[i * RN + r].x = x;
                 }
@@ -301,10 +313,7 @@ __device__ __forceinline__ void exchange(cplx<R>* v, cplx<R>* lds, int t) {
             bmap<L, C, NT, MODE, RAD>(t, i, q, j);
             const int ob = (j / NS) * NS * RAD + (j % NS);
 #pragma unroll
-            for (int r = 0; r < RAD; ++r) {
-                const int e = ob + r * NS;
-                lds[LY::idx(q, e) + CP::add(e)] = v[i * RAD + r];
-            }
+            for (int r = 0; r < RAD; ++r) lds[wslot(q, j, ob, r)] = v[i * RAD + r];
         }
         __syncthreads();
 #pragma unroll
@@ -312,10 +321,7 @@ __device__ __forceinline__ void exchange(cplx<R>* v, cplx<R>* lds, int t) {
             int q, j;
             bmap<L, C, NT, MODE, RN>(t, i, q, j);
 #pragma unroll
-            for (int r = 0; r < RN; ++r) {
-                const int e = j + r * (L / RN);
-                v[i * RN + r] = lds[LY::idx(q, e) + CP::add(e)];
-            }
+            for (int r = 0; r < RN; ++r) v[i * RN + r] = lds[rslot(q, j, r)];
         }
         __syncthreads();
     }
@@ -624,12 +630,12 @@ __device__ __forceinline__ void tab_stage_read(const cplx<R>* tb, cplx<R>* kt, c
     constexpr int LR = L / RAD;
     const bool mir = (col0 % L) >= L / 2;
     const int c = t % C;
-    const int q0 = mir ? C - 1 - c : c;
+    // entry t + m NT (row (t + m NT) / C, run position c) goes to slot
+    // row C + q0: a lane base plus m NT (NT is a multiple of C)
+    const int base = (t / C) * C + (mir ? C - 1 - c : c);
 #pragma unroll
-    for (int m = 0; m < TS::PER; ++m) {
-        const int idx = t + m * NT;
-        if (m + 1 < TS::PER || idx < TS::N) lds[(idx / C) * C + q0] = tb[m];
-    }
+    for (int m = 0; m < TS::PER; ++m)
+        if (m + 1 < TS::PER || t + m * NT < TS::N) lds[base + m * NT] = tb[m];
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < E / RAD; ++i) {
