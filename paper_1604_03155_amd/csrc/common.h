@@ -130,6 +130,13 @@ struct PassDesc {
 // 2N = 96 and 128 the table is L2-resident and the staging gains nothing.
 __host__ __device__ constexpr bool staged_fetch_length(int L) { return L == 192 || L == 256 || L == 512; }
 
+// Column tile width of the plain forward / inverse complex64 passes of
+// length 1024 (16 pencils, 128-byte rows, split exchange); 0: the length's
+// default width (8 there).  3D N = 512: those passes 1.39 / 1.34 ms with 8.
+__host__ __device__ constexpr int wide_col_C(int L, int mode, int kind, bool fp64) {
+    return (L == 1024 && mode == MODE_COL && !fp64 && (kind == KIND_FWD || kind == KIND_INV)) ? 16 : 0;
+}
+
 // ----------------------------------------------------- plan precompute ----
 struct GreensParams {
     int d;

@@ -848,26 +848,38 @@ constexpr bool row_needs_split() {
     return MODE == MODE_ROW && L * (int)sizeof(cplx<R>) > 65536;
 }
 
-template <typename R, int L, int MODE, int FK>
+// Wide column tiles: the plain forward and inverse complex64 column passes of
+// length 1024 take 16 pencils (128-byte tile rows) through the split
+// exchange (64 KiB), instead of the 8 pencils (64-byte rows) of the other
+// kinds at that length; see wide_col_C.
+template <typename R, int L, int MODE, int FK, int C>
+constexpr bool wide_col() {
+    return sizeof(R) == 4 && MODE == MODE_COL && L == 1024 && C == 16 && (FK == FK_FWD || FK == FK_INV);
+}
+
+template <typename R, int L, int MODE, int FK, int C = 0>
 struct Policy {
     static constexpr bool twl = L * (int)sizeof(cplx<R>) <= 8192 && make_plan(L, kMaxRad<R>).n >= 2;
+    static constexpr bool wide = wide_col<R, L, MODE, FK, C>();
     static constexpr bool split =
         (sizeof(R) == 4 && MODE == MODE_COL && (FK == FK_FUSED || FK == FK_FUSED_DERIV) && (L == 512 || L == 1024)) ||
-        (sizeof(R) == 4 && MODE == MODE_ROW && FK == FK_INV && (L == 512 || L >= 8192)) ||
+        (sizeof(R) == 4 && MODE == MODE_ROW && FK == FK_INV && (L == 512 || L >= 8192)) || wide ||
         row_needs_split<R, L, MODE>();
-    // the two-output kinds (two spectra per thread) keep the default budget
-    static constexpr int min_waves = (split && sizeof(R) == 4 && FK != FK_INV_GRAD && FK != FK_FUSED_GRAD) ? 3 : 1;
+    // the two-output kinds (two spectra per thread) keep the default budget;
+    // wide tiles (8 waves) fit two workgroups per CU at 4 waves per SIMD
+    static constexpr int min_waves =
+        wide ? 4 : ((split && sizeof(R) == 4 && FK != FK_INV_GRAD && FK != FK_FUSED_GRAD) ? 3 : 1);
 };
 
 // The C2R rows (FS & 7 == 4) stage whole complex values in LDS and keep the
 // plain exchange.
-template <typename R, int L, int MODE, int FK, int FS>
+template <typename R, int L, int MODE, int FK, int FS, int C = 0>
 constexpr bool use_split() {
-    return Policy<R, L, MODE, FK>::split && ((FS & 7) != 4 || row_needs_split<R, L, MODE>());
+    return Policy<R, L, MODE, FK, C>::split && ((FS & 7) != 4 || row_needs_split<R, L, MODE>());
 }
-template <typename R, int L, int MODE, int FK, int FS>
+template <typename R, int L, int MODE, int FK, int FS, int C = 0>
 constexpr int kernel_waves() {
-    return use_split<R, L, MODE, FK, FS>() ? Policy<R, L, MODE, FK>::min_waves : 1;
+    return use_split<R, L, MODE, FK, FS, C>() ? Policy<R, L, MODE, FK, C>::min_waves : 1;
 }
 
 // FS: 0 plain pass; 1 four-step step A (forward, outputs times W^{o e});
@@ -882,7 +894,7 @@ __device__ __forceinline__ void tile_body(cplx<R>* v, cplx<R>* kt, cplx<R>* lds,
     constexpr RP F = make_plan(L, kMaxRad<R>);
     constexpr RP I = reversed(F);
     constexpr int E = C * L / NT;
-    constexpr bool SP = use_split<R, L, MODE, FK, FS>();
+    constexpr bool SP = use_split<R, L, MODE, FK, FS, C>();
     cplx<R>* __restrict__ gout = reinterpret_cast<cplx<R>*>(p.out);
     cplx<R>* __restrict__ gout2 = reinterpret_cast<cplx<R>*>(p.out2);
     const R ks = (R)p.kscale;
@@ -937,7 +949,7 @@ __device__ __forceinline__ void tile_body(cplx<R>* v, cplx<R>* kt, cplx<R>* lds,
 // One tile (tile index b of the pass described by p).
 template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX, int FS>
 __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
-    using PO = Policy<R, L, MODE, FK>;
+    using PO = Policy<R, L, MODE, FK, C>;
     constexpr RP F = make_plan(L, kMaxRad<R>);
     constexpr RP I = reversed(F);
     constexpr int E = C * L / NT;
@@ -947,9 +959,9 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
     constexpr bool HALF = (FS & 8) != 0;
     constexpr bool FULL = (FS & 16) != 0;
     constexpr int NIN = (FL && FSB != 2) ? L / 2 : L;
-    using LY = Lay<L, C, MODE, (int)sizeof(cplx<R>), use_split<R, L, MODE, FK, FS>() ? 65536 : kPadLimit>;
+    using LY = Lay<L, C, MODE, (int)sizeof(cplx<R>), use_split<R, L, MODE, FK, FS, C>() ? 65536 : kPadLimit>;
     constexpr int LYP = LY::size + ((MODE == MODE_COL && FK == FK_FUSED && FS == 0) ? col_pad_slots<L, C, F>() : 0);
-    constexpr int NLDS0 = use_split<R, L, MODE, FK, FS>() ? (LYP + 1) / 2 : LYP;
+    constexpr int NLDS0 = use_split<R, L, MODE, FK, FS, C>() ? (LYP + 1) / 2 : LYP;
     // staged Khat fetch: plain fused complex64 columns of the staged lengths
     constexpr bool STG = FK == FK_FUSED && FSB == 0 && !HALF && !FULL && MODE == MODE_COL && D == 3 &&
                          sizeof(R) == 4 && staged_fetch_length(L) && C == 16;
@@ -980,7 +992,7 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
         if constexpr (STG) {
             // the tile's table entries wait in tb until the forward transform
             // is done (the dispatcher checks that the table has the boundary block)
-            constexpr bool SP = use_split<R, L, MODE, FK, FS>();
+            constexpr bool SP = use_split<R, L, MODE, FK, FS, C>();
             cplx<R> tb[TabStage<L, C, NT>::PER];
             tab_stage_issue<R, L, C, NT, CPLX>(tb, p, tl.col0, t);
             expand<R, L, C, NT, PL, NIN>(v, vn);
@@ -1031,7 +1043,7 @@ __device__ __forceinline__ unsigned tile_order(const PassDesc& p, unsigned b) {
 
 // One tile per workgroup.
 template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX, int FS>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kernel_waves<R, L, MODE, FK, FS>())))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kernel_waves<R, L, MODE, FK, FS, C>())))
 fast_kernel(PassDesc p) {
     unsigned b = blockIdx.x;
     if (p.xcd_map) b = tile_order<L, C, MODE, FK, D, FS>(p, xcd_tile(b, gridDim.x));
@@ -1042,7 +1054,7 @@ fast_kernel(PassDesc p) {
 // descriptor each, same length and kind); item i owns the workgroups
 // [starts[i], starts[i + 1]).
 template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX, int FS>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kernel_waves<R, L, MODE, FK, FS>())))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kernel_waves<R, L, MODE, FK, FS, C>())))
 fast_group_kernel(const PassDesc* __restrict__ descs, const unsigned* __restrict__ starts, int nitems) {
     const unsigned b = xcd_tile(blockIdx.x, gridDim.x);
     int i = 0;
@@ -1192,6 +1204,19 @@ constexpr Shape shape_for(int L, int mode, int esize) {
 template <typename R, int L, int MODE, bool GROUP>
 hipError_t launch_len_mode(const PassDesc& p, int kind, hipStream_t s, const GroupArgs* ga) {
     constexpr Shape S = shape_for(L, MODE, (int)sizeof(cplx<R>));
+    if constexpr (wide_col<R, L, MODE, FK_FWD, 16>()) {
+        // wide column tiles (plain forward / inverse passes only)
+        if (p.C == 16) {
+            constexpr int C = 16, NT = C * L / S.E;
+            if (p.real_mode || p.post_tw || p.fs_L1 || (kind != KIND_FWD && kind != KIND_INV))
+                return hipErrorInvalidValue;
+            const long long nblocks = GROUP ? (long long)ga->ntiles : (long long)p.outer * ((p.inner + C - 1) / C);
+            if (nblocks <= 0) return hipSuccess;
+            if (nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+            if (kind == KIND_FWD) return launch_k<R, L, C, NT, MODE, FK_FWD, 3, false, 0, GROUP>(p, nblocks, s, ga);
+            return launch_k<R, L, C, NT, MODE, FK_INV, 3, false, 0, GROUP>(p, nblocks, s, ga);
+        }
+    }
     if constexpr (S.C == 0) {
         return hipErrorInvalidValue;
     } else {

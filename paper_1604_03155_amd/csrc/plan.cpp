@@ -490,7 +490,8 @@ int choose_C(const vg_plan* p, const PassStep& st, bool* specialised) {
                                                             st.kind == KIND_FUSED_DERIV) &&
                                                            d.fs_L1 && d.post_tw == 2 && p->d == 2)));
     if (four_ok && !p->cfg.generic && !std::getenv("VG_GENERIC_PASSES")) {
-        const int fc = fast_pass_C(d.L, st.mode, p->fp64);
+        const int wc = four ? 0 : wide_col_C(d.L, st.mode, st.kind, p->fp64);
+        const int fc = wc ? wc : fast_pass_C(d.L, st.mode, p->fp64);
         const bool rowm = st.mode == MODE_ROW;
         if (fc > 0 && fast_pass_fits(d.L, st.mode, p->fp64, d.in_se, d.out_se, rowm ? d.in_so : 1, rowm ? d.out_so : 1)) {
             *specialised = true;
