@@ -227,6 +227,16 @@ __device__ __forceinline__ cplx<R> twmul(cplx<R> v, cplx<R> w) {
     return DIR < 0 ? cmul(v, w) : cmulc(v, w);
 }
 
+// Stage twiddles of lengths whose table (L entries) is too large for the
+// workgroup's LDS copy: two small tables in LDS, tw[0, 64) = W^i and
+// tw[64 + i] = W^(64 i), and W^m = W^(64 (m / 64)) W^(m % 64) (one more
+// complex product, about one more rounding; the global table had cost the
+// 2D N = 4096 rows of length 8192 a third of their time).
+template <typename R, int L>
+constexpr bool tw_split() {
+    return L * (int)sizeof(cplx<R>) > 8192 && L % 64 == 0 && make_plan(L, kMaxRad<R>).n >= 2;
+}
+
 // twiddles and butterflies of stage s of plan P for all of this thread's butterflies
 template <typename R, int L, int C, int NT, int MODE, int DIR, RP P, int s>
 __device__ __forceinline__ void compute_stage(cplx<R>* v, int t, const cplx<R>* __restrict__ tw) {
@@ -243,8 +253,13 @@ __device__ __forceinline__ void compute_stage(cplx<R>* v, int t, const cplx<R>* 
             const int k = j % NS;
             constexpr int STW = L / (NS * RAD);
 #pragma unroll
-            for (int r = 1; r < RAD; ++r)
-                v[i * RAD + r] = twmul<DIR>(v[i * RAD + r], ld_off<cplx<R>>(tw, (unsigned)(r * k * STW) * sizeof(cplx<R>)));
+            for (int r = 1; r < RAD; ++r) {
+                const unsigned m = (unsigned)(r * k * STW);
+                cplx<R> w;
+                if constexpr (tw_split<R, L>()) w = cmul(tw[64 + (m >> 6)], tw[m & 63u]);
+                else w = ld_off<cplx<R>>(tw, m * (unsigned)sizeof(cplx<R>));
+                v[i * RAD + r] = twmul<DIR>(v[i * RAD + r], w);
+            }
         }
         dft_fixed<RAD, DIR>(&v[i * RAD]);
     }
@@ -971,11 +986,16 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
     __shared__ cplx<R> lds[NLDS];
     __shared__ cplx<R> twl[PO::twl ? L : 1];
     const cplx<R>* __restrict__ tw = reinterpret_cast<const cplx<R>*>(p.tw);
+    constexpr bool TWS = tw_split<R, L>();
+    __shared__ cplx<R> tws[TWS ? 64 + L / 64 : 1];
     if constexpr (PO::twl) {
         // copied once per workgroup; first read after the barrier of the
         // first exchange (stage 0 of every plan runs without twiddles)
         for (int i = threadIdx.x; i < L; i += NT) twl[i] = tw[i];
         tw = twl;
+    } else if constexpr (TWS) {
+        for (int i = threadIdx.x; i < 64 + L / 64; i += NT) tws[i] = tw[i < 64 ? i : (i - 64) * 64];
+        tw = tws;
     }
     const int t = threadIdx.x;
     const FTile tl = fast_tile<C, MODE>(p, b);
