@@ -1066,7 +1066,21 @@ template <typename R, int L, int C, int NT, int MODE, int FK, int D, bool CPLX, 
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kernel_waves<R, L, MODE, FK, FS, C>())))
 fast_kernel(PassDesc p) {
     unsigned b = blockIdx.x;
-    if (p.xcd_map) b = tile_order<L, C, MODE, FK, D, FS>(p, xcd_tile(b, gridDim.x));
+    if constexpr ((FK == FK_FUSED || FK == FK_FUSED_DERIV || FK == FK_FUSED_GRAD) && (FS & 7) == 2 && (FS & 16) == 0 &&
+                  MODE == MODE_COL) {
+        // four-step step B (2D, octant table): tile (k1 = o, column block).
+        // Spectral index o + L1 e mirrors to (L1 - o) + L1 (L2 - 1 - e) and
+        // column c to 2N - c, so tiles o and L1 - o, and mirrored column
+        // blocks, read the same table entries: launch them next to each
+        // other, in launch order (2D N = 4096: 0.246 -> 0.231 ms; with the
+        // XCD-grouped order 0.237 ms)
+        const unsigned nt = (unsigned)((p.inner + C - 1) / C);
+        const unsigned no = (unsigned)p.outer;
+        if (nt * no == gridDim.x && (no & 1u) == 0u && (nt & 1u) == 0u)
+            b = mirror_row(b / nt, no) * nt + mirror_tile(b % nt, nt);
+    } else if (p.xcd_map) {
+        b = tile_order<L, C, MODE, FK, D, FS>(p, xcd_tile(b, gridDim.x));
+    }
     fast_run<R, L, C, NT, MODE, FK, D, CPLX, FS>(p, b);
 }
 
