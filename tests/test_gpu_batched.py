@@ -167,6 +167,27 @@ def test_batched_mixed_dimensions_and_ungrouped_paths(monkeypatch):
         assert torch.equal(a, b), i
 
 
+def test_batched_wide_column_tiles():
+    """Two 3D N = 512 densities (plain column passes of length 1024 on 16-pencil
+    tiles, grouped into one launch per stage) next to a small one: bitwise
+    equal to single applies."""
+    say("wide column batch")
+    vg = _vg()
+    torch = _torch()
+    specs = [(3, 512, "helmholtz", 150.0), (3, 512, "laplace", 0.0), (3, 64, "helmholtz", 20.0)]
+    plans = [vg.Plan(d, N, kind, k, precision="fp32") for d, N, kind, k in specs]
+    rng = np.random.default_rng(512)
+    fs = [torch.from_numpy((rng.standard_normal((N,) * d) + 1j * rng.standard_normal((N,) * d)).astype(np.complex64)).cuda()
+          for d, N, _, _ in specs]
+    ref = singles(plans, fs)
+    out = vg.apply_batched(plans, fs)
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(out, ref)):
+        assert torch.equal(a, b), i
+    del plans, fs, ref, out
+    torch.cuda.empty_cache()
+
+
 def test_batched_fp64_matches_single_applies():
     say("fp64 batch")
     vg = _vg()
