@@ -87,7 +87,7 @@ struct PassDesc {
     // starting at k3 = 16 m are whole 128-byte lines (complex64); 2D tables
     // and 3D N < 96: N + 1
     int tab_pitch;
-    // staged table fetch (3D FP32, staged_fetch_length(2N)): element offset
+    // staged table fetch (3D FP32, staged_bnd_length(2N)): element offset
     // in `table` of the boundary block, which repeats the entries
     // k3 = 16 (b + 1), b < N / 16, of every row in the order [k2][b][k1];
     // 0 when absent
@@ -125,10 +125,16 @@ struct PassDesc {
 };
 
 // Fused 3D column passes whose complex64 kernel stages the Khat tile through
-// LDS (tiles of 16 columns); their plans' FP32 tables carry the boundary
-// block (PassDesc::tab_bnd).  Measured faster at 2N = 192, 256 and 512; at
-// 2N = 96 and 128 the table is L2-resident and the staging gains nothing.
-__host__ __device__ constexpr bool staged_fetch_length(int L) { return L == 192 || L == 256 || L == 512; }
+// LDS: the tile width (columns) of the staged kernel, 0 where the entries are
+// fetched per thread.  Measured faster at 2N = 192, 256, 512 (tiles of 16)
+// and 1024 (tiles of 8); at 2N = 96 and 128 the table is L2-resident and the
+// staging gains nothing.
+__host__ __device__ constexpr int staged_fetch_C(int L) {
+    return (L == 192 || L == 256 || L == 512) ? 16 : (L == 1024 ? 8 : 0);
+}
+// The staged lengths with 16-column tiles, whose plans' FP32 tables carry the
+// boundary block (PassDesc::tab_bnd) so that every run they read is one line.
+__host__ __device__ constexpr bool staged_bnd_length(int L) { return staged_fetch_C(L) == 16; }
 
 // Column tile width of the plain forward / inverse complex64 passes of
 // length 1024 (16 pencils, 128-byte rows, split exchange); 0: the length's

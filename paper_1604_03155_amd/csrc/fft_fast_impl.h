@@ -590,19 +590,21 @@ __device__ __forceinline__ void table_fetch(cplx<R>* kt, const void* __restrict_
 }
 
 // Staged Khat fetch (3D fused column passes over the octant table, tiles of
-// C = 16 adjacent columns k3 = k3_0 + q of one spectral row k2, k3_0 and N
-// multiples of 16).  The tile needs, for every k1 = 0 .. L/2, 16 consecutive
-// octant entries: k3' = k3_0 .. k3_0 + 15, or, for mirrored columns
-// (k3_0 >= L/2), k3' = L - k3_0 - 15 .. L - k3_0.  With the row pitch a
-// multiple of 16 the first run is one 128-byte line; of the second, the
-// first 15 entries are one line and the last (k3' = L - k3_0, a multiple of
-// 16) comes from the boundary block, where the entries of consecutive k1 are
-// adjacent.  Every entry is loaded once, at the start of the tile (lane c of
+// C = 16 or 8 adjacent columns k3 = k3_0 + q of one spectral row k2, k3_0
+// and N multiples of C).  The tile needs, for every k1 = 0 .. L/2, C
+// consecutive octant entries: k3' = k3_0 .. k3_0 + C - 1, or, for mirrored
+// columns (k3_0 >= L/2), k3' = L - k3_0 - (C - 1) .. L - k3_0.  With the row
+// pitch a multiple of 16 the first run is one 128-byte line (C = 16) or half
+// of one (C = 8).  C = 16: of the second, the first 15 entries are one line
+// and the last (k3' = L - k3_0, a multiple of 16) comes from the boundary
+// block, where the entries of consecutive k1 are adjacent.  C = 8 (no
+// boundary block): the mirrored run is read in place; it crosses a line
+// when L - k3_0 is a multiple of 16.  Every entry is loaded once, at the start of the tile (lane c of
 // each group of 16 takes run position c), and goes to LDS after the forward
 // transform, where each thread picks the values of its spectral indices.
 template <int L, int C, int NT>
 struct TabStage {
-    static_assert(C == 16 && NT % C == 0, "tiles of 16 columns");
+    static_assert((C == 16 || C == 8) && NT % C == 0, "tiles of 16 or 8 columns");
     static constexpr int ROWS = L / 2 + 1;
     static constexpr int N = ROWS * C;
     static constexpr int PER = (N + NT - 1) / NT;
@@ -620,7 +622,7 @@ __device__ __forceinline__ void tab_stage_issue(cplx<R>* tb, const PassDesc& p, 
     const unsigned row0 = (unsigned)(t / C);
     // entry offset of row k1 = row0 + m NT / C: base + m * stride
     unsigned base, stride;
-    if (mir && c == C - 1) {
+    if (C == 16 && mir && c == C - 1) {
         base = p.tab_bnd + (k2f * nb + (unsigned)(L - k3) / 16u - 1u) * N1 + row0;
         stride = NT / C;
     } else {
@@ -984,7 +986,7 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
     constexpr int NLDS0 = use_split<R, L, MODE, FK, FS, C>() ? (LYP + 1) / 2 : LYP;
     // staged Khat fetch: plain fused complex64 columns of the staged lengths
     constexpr bool STG = FK == FK_FUSED && FSB == 0 && !HALF && !FULL && MODE == MODE_COL && D == 3 &&
-                         sizeof(R) == 4 && staged_fetch_length(L) && C == 16;
+                         sizeof(R) == 4 && C == staged_fetch_C(L);
     constexpr int NLDS1 = (FSB == 4 && C * (L + 1) > NLDS0) ? C * (L + 1) : NLDS0;
     constexpr int NSTG = STG ? (L / 2 + 1) * C : 0;  // TabStage::N
     constexpr int NLDS = NSTG > NLDS1 ? NSTG : NLDS1;
@@ -1016,7 +1018,8 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
         issue_loads<R, L, C, NT, MODE, PL, NIN>(vn, gin, tl, p.in_se, t);
         if constexpr (STG) {
             // the tile's table entries wait in tb until the forward transform
-            // is done (the dispatcher checks that the table has the boundary block)
+            // is done (with 16-column tiles the dispatcher checks that the table
+            // has the boundary block)
             constexpr bool SP = use_split<R, L, MODE, FK, FS, C>();
             cplx<R> tb[TabStage<L, C, NT>::PER];
             tab_stage_issue<R, L, C, NT, CPLX>(tb, p, tl.col0, t);
@@ -1173,7 +1176,7 @@ hipError_t launch_shape(const PassDesc& p, int kind, hipStream_t s, const GroupA
             return p.table_complex ? by_kind(I2{}, T_{}, I2{}) : by_kind(I2{}, F_{}, I2{});
         }
         // the staged fetch of plain fused passes needs the table's boundary block
-        if (sizeof(R) == 4 && staged_fetch_length(L) && C == 16 && p.d == 3 && kind == KIND_FUSED && !p.tab_bnd)
+        if (sizeof(R) == 4 && staged_bnd_length(L) && C == 16 && p.d == 3 && kind == KIND_FUSED && !p.tab_bnd)
             return hipErrorInvalidValue;
         if (p.d == 3) return p.table_complex ? by_kind(I3{}, T_{}, I0{}) : by_kind(I3{}, F_{}, I0{});
         return p.table_complex ? by_kind(I2{}, T_{}, I0{}) : by_kind(I2{}, F_{}, I0{});

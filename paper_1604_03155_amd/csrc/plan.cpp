@@ -405,7 +405,7 @@ vg_status precompute(vg_plan* p, hipStream_t s, bool keep_T) {
     const long long rows = nK / N1;
     p->tab_pitch = (d == 3 && N >= 96) ? (int)((N1 + 15) / 16 * 16) : (int)N1;
     const long long nPad = rows * p->tab_pitch;
-    const int nb = (d == 3 && !p->fp64 && N % 16 == 0 && staged_fetch_length(2 * N)) ? N / 16 : 0;
+    const int nb = (d == 3 && !p->fp64 && N % 16 == 0 && staged_bnd_length(2 * N)) ? N / 16 : 0;
     p->tab_bnd = nb ? (unsigned)nPad : 0u;
     p->table_alg_bytes = (size_t)nK * esz;
     p->table_bytes = (size_t)(nPad + (long long)nb * N1 * N1) * esz;
