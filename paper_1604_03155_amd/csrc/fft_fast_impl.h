@@ -984,9 +984,10 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
     using LY = Lay<L, C, MODE, (int)sizeof(cplx<R>), use_split<R, L, MODE, FK, FS, C>() ? 65536 : kPadLimit>;
     constexpr int LYP = LY::size + ((MODE == MODE_COL && FK == FK_FUSED && FS == 0) ? col_pad_slots<L, C, F>() : 0);
     constexpr int NLDS0 = use_split<R, L, MODE, FK, FS, C>() ? (LYP + 1) / 2 : LYP;
-    // staged Khat fetch: plain fused complex64 columns of the staged lengths
-    constexpr bool STG = FK == FK_FUSED && FSB == 0 && !HALF && !FULL && MODE == MODE_COL && D == 3 &&
-                         sizeof(R) == 4 && C == staged_fetch_C(L);
+    // staged Khat fetch: plain fused and fused-derivative complex64 columns of
+    // the staged lengths (derivative kind at 3D N = 512: 0.15 ms per gradient)
+    constexpr bool STG = (FK == FK_FUSED || FK == FK_FUSED_DERIV) && FSB == 0 && !HALF && !FULL &&
+                         MODE == MODE_COL && D == 3 && sizeof(R) == 4 && C == staged_fetch_C(L);
     constexpr int NLDS1 = (FSB == 4 && C * (L + 1) > NLDS0) ? C * (L + 1) : NLDS0;
     constexpr int NSTG = STG ? (L / 2 + 1) * C : 0;  // TabStage::N
     constexpr int NLDS = NSTG > NLDS1 ? NSTG : NLDS1;
@@ -1024,11 +1025,13 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
             cplx<R> tb[TabStage<L, C, NT>::PER];
             tab_stage_issue<R, L, C, NT, CPLX>(tb, p, tl.col0, t);
             expand<R, L, C, NT, PL, NIN>(v, vn);
-            run_from<R, L, C, NT, MODE, -1, F, 0, SP, true>(v, lds, t, tw);
+            constexpr bool CPD = FK == FK_FUSED;  // exchange padding: plain fused kind only
+            run_from<R, L, C, NT, MODE, -1, F, 0, SP, CPD>(v, lds, t, tw);
             tab_stage_read<R, L, C, NT, F>(tb, kt, lds, tl.col0, t);
             table_apply<R, E, CPLX>(v, kt);
+            if constexpr (FK == FK_FUSED_DERIV) deriv_copy<R, L, C, NT, MODE, F.r[F.n - 1]>(v, v, (R)p.kscale, t);
             __syncthreads();  // the inverse's first exchange overwrites the staged entries
-            run_from<R, L, C, NT, MODE, +1, I, 0, SP, true>(v, lds, t, tw);
+            run_from<R, L, C, NT, MODE, +1, I, 0, SP, CPD>(v, lds, t, tw);
             store_global<R, L, C, NT, MODE, I, L / 2>(v, reinterpret_cast<cplx<R>*>(p.out), tl, p.out_se, t);
             return;
         }
@@ -1176,7 +1179,8 @@ hipError_t launch_shape(const PassDesc& p, int kind, hipStream_t s, const GroupA
             return p.table_complex ? by_kind(I2{}, T_{}, I2{}) : by_kind(I2{}, F_{}, I2{});
         }
         // the staged fetch of plain fused passes needs the table's boundary block
-        if (sizeof(R) == 4 && staged_bnd_length(L) && C == 16 && p.d == 3 && kind == KIND_FUSED && !p.tab_bnd)
+        if (sizeof(R) == 4 && staged_bnd_length(L) && C == 16 && p.d == 3 &&
+            (kind == KIND_FUSED || kind == KIND_FUSED_DERIV) && !p.tab_bnd)
             return hipErrorInvalidValue;
         if (p.d == 3) return p.table_complex ? by_kind(I3{}, T_{}, I0{}) : by_kind(I3{}, F_{}, I0{});
         return p.table_complex ? by_kind(I2{}, T_{}, I0{}) : by_kind(I2{}, F_{}, I0{});

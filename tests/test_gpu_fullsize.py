@@ -10,7 +10,8 @@ stream), against the FP64 oracle on the whole grid:
     N = 256 also the FP32 gradient at 1e-5;
   * the same N = 256 plan applied twice in a row to different densities
     (workspace reuse) and to the density in place;
-  * 3D N = 256 FP32 with the real tables (Laplace, biharmonic) on white noise.
+  * 3D N = 256 FP32 with the real tables (Laplace, biharmonic) on white
+    noise, potential and gradient.
 
 The 2D N = 4096, batched and N = 512 configurations are held to the oracle or
 closed forms in test_gpu_parity.py, test_gpu_batched.py and
@@ -78,8 +79,9 @@ def test_laplace3d_n32_fp64_oracle_and_closed_form():
 @pytest.mark.parametrize("kernel", ["laplace", "biharmonic"])
 def test_real_table_n256_fp32(kernel):
     """3D N = 256 FP32 with a real Khat table (the staged fetch's real-valued
-    variant, padded table and boundary block) against the oracle on the
-    whole grid, white-noise density."""
+    variant, padded table and boundary block; for the gradient also its
+    derivative kind) against the oracle on the whole grid, white-noise
+    density: potential and gradient."""
     say("real table n256", kernel)
     import torch
 
@@ -88,11 +90,18 @@ def test_real_table_n256_fp32(kernel):
     N = 256
     rng = np.random.default_rng(2560)
     f = rng.standard_normal((N,) * 3) + 1j * rng.standard_normal((N,) * 3)
-    ref = op.Plan(3, N, kernel).apply(f)
+    o = op.Plan(3, N, kernel)
+    ref = o.apply(f)
     p = vg.Plan(3, N, kernel, precision="fp32")
-    out = p.apply(torch.from_numpy(f.astype(np.complex64)).cuda())
+    x = torch.from_numpy(f.astype(np.complex64)).cuda()
+    out = p.apply(x)
+    phi, grad = p.gradient(x)
     torch.cuda.synchronize()
     check(out.cpu().numpy(), ref, FP32_TOL, f"{kernel} fp32 apply")
+    check(phi.cpu().numpy(), ref, FP32_TOL, f"{kernel} fp32 potential of the gradient call")
+    gref = o.gradient(f)
+    for j in range(3):
+        check(grad[j].cpu().numpy(), gref[j], FP32_TOL, f"{kernel} fp32 grad {j}")
 
 
 @pytest.mark.parametrize("name", ["helmholtz3d_k20_n128", "helmholtz3d_k20_n256"])
