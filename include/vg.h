@@ -120,7 +120,8 @@ typedef struct vg_plan_info {
     size_t table_bytes;       /* device bytes of the kernel table kept for applies: the Khat octant
                                  ((N+1)^d entries; 3D rows padded to 16 entries from N = 96 on;
                                  FP32 3D N = 96, 128, 256 add a block repeating every 16th k3
-                                 entry) or, for the convection kernel, the full (2N)^d table */
+                                 entry, complex N = 512 every 8th) or, for the convection
+                                 kernel, the full (2N)^d table */
     size_t workspace_bytes;   /* vg_workspace_size */
     size_t gradient_workspace_bytes;
     int tune;                 /* vg_tune_mode the plan was created with */

@@ -87,10 +87,10 @@ struct PassDesc {
     // starting at k3 = 16 m are whole 128-byte lines (complex64); 2D tables
     // and 3D N < 96: N + 1
     int tab_pitch;
-    // staged table fetch (3D FP32, staged_bnd_length(2N)): element offset
-    // in `table` of the boundary block, which repeats the entries
-    // k3 = 16 (b + 1), b < N / 16, of every row in the order [k2][b][k1];
-    // 0 when absent
+    // staged table fetch (3D FP32, C = staged_fetch_C(2N) > 0; C = 8: complex
+    // tables only): element offset in `table` of the boundary block, which
+    // repeats the entries k3 = C (b + 1), b < N / C, of every row in the
+    // order [k2][b][k1]; 0 when absent
     unsigned tab_bnd;
     int table_complex;      // 0: real table (Laplace), 1: complex
     // spectral derivative along this pass's axis (gradient kinds): i*kappa,
@@ -126,15 +126,14 @@ struct PassDesc {
 
 // Fused 3D column passes whose complex64 kernel stages the Khat tile through
 // LDS: the tile width (columns) of the staged kernel, 0 where the entries are
-// fetched per thread.  Measured faster at 2N = 192, 256, 512 (tiles of 16)
-// and 1024 (tiles of 8); at 2N = 96 and 128 the table is L2-resident and the
-// staging gains nothing.
+// fetched per thread.  Their plans' FP32 tables (complex ones only at width
+// 8) carry the boundary block (PassDesc::tab_bnd) at that stride, so that
+// every run they read sits in one line.  Measured faster at 2N = 192, 256, 512 (tiles of 16) and 1024
+// (tiles of 8); at 2N = 96 and 128 the table is L2-resident and the staging
+// gains nothing.
 __host__ __device__ constexpr int staged_fetch_C(int L) {
     return (L == 192 || L == 256 || L == 512) ? 16 : (L == 1024 ? 8 : 0);
 }
-// The staged lengths with 16-column tiles, whose plans' FP32 tables carry the
-// boundary block (PassDesc::tab_bnd) so that every run they read is one line.
-__host__ __device__ constexpr bool staged_bnd_length(int L) { return staged_fetch_C(L) == 16; }
 
 // Column tile width of the plain forward / inverse complex64 passes of
 // length 1024 (16 pencils, 128-byte rows, split exchange); 0: the length's
@@ -190,10 +189,10 @@ hipError_t launch_cos_contract(const c64* in, c64* out, const double* cmat, long
                                int Nout, long long I, hipStream_t s);
 // FP64 octant (rows of N1 entries, dense) -> the kernel table: rows at pitch
 // `pitch`, rounded to FP32 (to_fp32) and kept complex or real; with nb > 0
-// (3D), entries k3 = 16 (b + 1), b < nb, are also written to the boundary
+// (3D), entries k3 = bs (b + 1), b < nb, are also written to the boundary
 // block at element offset bnd, index (k2 nb + b) N1 + k1.
 hipError_t launch_round_table(const c64* in, void* out, long long rows, int N1, int pitch, int to_fp32,
-                              int complex_out, long long bnd, int nb, hipStream_t s);
+                              int complex_out, long long bnd, int nb, int bs, hipStream_t s);
 // First contraction on the full lattice (g.full): rows = M^(d-1), K = M.
 hipError_t launch_greens_contract_full(const GreensParams& g, int n_out, const double* cmat, c64* out,
                                        hipStream_t s);

@@ -595,11 +595,12 @@ __device__ __forceinline__ void table_fetch(cplx<R>* kt, const void* __restrict_
 // consecutive octant entries: k3' = k3_0 .. k3_0 + C - 1, or, for mirrored
 // columns (k3_0 >= L/2), k3' = L - k3_0 - (C - 1) .. L - k3_0.  With the row
 // pitch a multiple of 16 the first run is one 128-byte line (C = 16) or half
-// of one (C = 8).  C = 16: of the second, the first 15 entries are one line
-// and the last (k3' = L - k3_0, a multiple of 16) comes from the boundary
-// block, where the entries of consecutive k1 are adjacent.  C = 8 (no
-// boundary block): the mirrored run is read in place; it crosses a line
-// when L - k3_0 is a multiple of 16.  Every entry is loaded once, at the start of the tile (lane c of
+// of one (C = 8); of the second, the first C - 1 entries sit in one line and
+// the last (k3' = L - k3_0, a multiple of C) comes from the boundary block,
+// where the entries of consecutive k1 are adjacent.  Real tables with C = 8
+// (32-byte runs, which cross a line once in four) have no boundary block and
+// read the mirrored run in place: the extra request per run measured slower
+// there (3D N = 512 Laplace fused pass 2.72 -> 2.75-2.79 ms).  Every entry is loaded once, at the start of the tile (lane c of
 // each group of 16 takes run position c), and goes to LDS after the forward
 // transform, where each thread picks the values of its spectral indices.
 template <int L, int C, int NT>
@@ -614,7 +615,7 @@ template <typename R, int L, int C, int NT, bool CPLX>
 __device__ __forceinline__ void tab_stage_issue(cplx<R>* tb, const PassDesc& p, int col0, int t) {
     using TS = TabStage<L, C, NT>;
     constexpr unsigned ES = CPLX ? sizeof(cplx<R>) : sizeof(R);
-    const unsigned N1 = (unsigned)p.tabN + 1u, tp = (unsigned)p.tab_pitch, nb = (unsigned)p.tabN / 16u;
+    const unsigned N1 = (unsigned)p.tabN + 1u, tp = (unsigned)p.tab_pitch, nb = (unsigned)p.tabN / (unsigned)C;
     const int k2 = col0 / L, k3 = col0 % L;
     const unsigned k2f = (unsigned)min(k2, L - k2);
     const bool mir = k3 >= L / 2;
@@ -622,8 +623,8 @@ __device__ __forceinline__ void tab_stage_issue(cplx<R>* tb, const PassDesc& p, 
     const unsigned row0 = (unsigned)(t / C);
     // entry offset of row k1 = row0 + m NT / C: base + m * stride
     unsigned base, stride;
-    if (C == 16 && mir && c == C - 1) {
-        base = p.tab_bnd + (k2f * nb + (unsigned)(L - k3) / 16u - 1u) * N1 + row0;
+    if ((CPLX || C == 16) && mir && c == C - 1) {
+        base = p.tab_bnd + (k2f * nb + (unsigned)(L - k3) / (unsigned)C - 1u) * N1 + row0;
         stride = NT / C;
     } else {
         base = row0 * N1 * tp + k2f * tp + (unsigned)(mir ? L - k3 - (C - 1) : k3) + (unsigned)c;
@@ -1019,8 +1020,7 @@ __device__ __forceinline__ void fast_run(const PassDesc& p, unsigned b) {
         issue_loads<R, L, C, NT, MODE, PL, NIN>(vn, gin, tl, p.in_se, t);
         if constexpr (STG) {
             // the tile's table entries wait in tb until the forward transform
-            // is done (with 16-column tiles the dispatcher checks that the table
-            // has the boundary block)
+            // is done (the dispatcher checks that the table has the boundary block)
             constexpr bool SP = use_split<R, L, MODE, FK, FS, C>();
             cplx<R> tb[TabStage<L, C, NT>::PER];
             tab_stage_issue<R, L, C, NT, CPLX>(tb, p, tl.col0, t);
@@ -1179,7 +1179,7 @@ hipError_t launch_shape(const PassDesc& p, int kind, hipStream_t s, const GroupA
             return p.table_complex ? by_kind(I2{}, T_{}, I2{}) : by_kind(I2{}, F_{}, I2{});
         }
         // the staged fetch of plain fused passes needs the table's boundary block
-        if (sizeof(R) == 4 && staged_bnd_length(L) && C == 16 && p.d == 3 &&
+        if (sizeof(R) == 4 && staged_fetch_C(L) == C && (C == 16 || p.table_complex) && p.d == 3 &&
             (kind == KIND_FUSED || kind == KIND_FUSED_DERIV) && !p.tab_bnd)
             return hipErrorInvalidValue;
         if (p.d == 3) return p.table_complex ? by_kind(I3{}, T_{}, I0{}) : by_kind(I3{}, F_{}, I0{});

@@ -315,7 +315,7 @@ vg_status precompute_full(vg_plan* p, hipStream_t s, bool keep_T) {
     p->tab_pitch = (int)L;
     p->tab_bnd = 0;
     if ((he = dev_malloc(&p->table, p->table_bytes)) != hipSuccess) return chk(he, "kernel table");
-    if ((he = launch_round_table(K.as<c64>(), p->table, nK / L, (int)L, (int)L, p->fp64 ? 0 : 1, 1, 0, 0, s)) !=
+    if ((he = launch_round_table(K.as<c64>(), p->table, nK / L, (int)L, (int)L, p->fp64 ? 0 : 1, 1, 0, 0, 0, s)) !=
         hipSuccess)
         return chk(he, "table rounding");
     (void)hipEventRecord(e1, s);
@@ -405,13 +405,15 @@ vg_status precompute(vg_plan* p, hipStream_t s, bool keep_T) {
     const long long rows = nK / N1;
     p->tab_pitch = (d == 3 && N >= 96) ? (int)((N1 + 15) / 16 * 16) : (int)N1;
     const long long nPad = rows * p->tab_pitch;
-    const int nb = (d == 3 && !p->fp64 && N % 16 == 0 && staged_bnd_length(2 * N)) ? N / 16 : 0;
+    const int bsc = (d == 3 && !p->fp64) ? staged_fetch_C(2 * N) : 0;
+    const int bs = (bsc == 16 || p->table_complex) ? bsc : 0;  // 8-wide: complex tables only
+    const int nb = (bs > 0 && N % bs == 0) ? N / bs : 0;
     p->tab_bnd = nb ? (unsigned)nPad : 0u;
     p->table_alg_bytes = (size_t)nK * esz;
     p->table_bytes = (size_t)(nPad + (long long)nb * N1 * N1) * esz;
     if ((he = dev_malloc(&p->table, p->table_bytes)) != hipSuccess) return chk(he, "kernel table");
     if ((he = launch_round_table(K.as<c64>(), p->table, rows, (int)N1, p->tab_pitch, p->fp64 ? 0 : 1,
-                                 p->table_complex, nPad, nb, s)) != hipSuccess)
+                                 p->table_complex, nPad, nb, bs, s)) != hipSuccess)
         return chk(he, "table rounding");
     (void)hipEventRecord(e1, s);
     if ((he = hipStreamSynchronize(s)) != hipSuccess) return chk(he, "precompute");

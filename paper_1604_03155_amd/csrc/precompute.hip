@@ -346,17 +346,17 @@ __device__ __forceinline__ void put_entry(void* out, long long i, c64 v, int to_
 
 // One thread per padded table slot: row r, entry e < pitch (pads are zero).
 __global__ void round_table_kernel(const c64* __restrict__ in, void* __restrict__ out, long long rows, int N1,
-                                   int pitch, int to_fp32, int complex_out, long long bnd, int nb) {
+                                   int pitch, int to_fp32, int complex_out, long long bnd, int nb, int bs) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= rows * pitch) return;
     const long long r = i / pitch;
     const int e = (int)(i - r * pitch);
     const c64 v = e < N1 ? in[r * N1 + e] : mk(0.0, 0.0);
     put_entry(out, i, v, to_fp32, complex_out);
-    if (nb > 0 && e >= 16 && (e & 15) == 0 && (e >> 4) <= nb) {
+    if (nb > 0 && e >= bs && e % bs == 0 && e / bs <= nb) {
         // r = k1 N1 + k2 (3D octant rows)
         const long long k1 = r / N1, k2 = r - (r / N1) * N1;
-        put_entry(out, bnd + (k2 * nb + ((e >> 4) - 1)) * N1 + k1, v, to_fp32, complex_out);
+        put_entry(out, bnd + (k2 * nb + (e / bs - 1)) * N1 + k1, v, to_fp32, complex_out);
     }
 }
 
@@ -398,13 +398,13 @@ hipError_t launch_cos_contract(const c64* in, c64* out, const double* cmat, long
 }
 
 hipError_t launch_round_table(const c64* in, void* out, long long rows, int N1, int pitch, int to_fp32,
-                              int complex_out, long long bnd, int nb, hipStream_t s) {
-    if (pitch < N1 || (nb > 0 && (N1 - 1) < 16 * nb)) return hipErrorInvalidValue;
+                              int complex_out, long long bnd, int nb, int bs, hipStream_t s) {
+    if (pitch < N1 || (nb > 0 && (bs <= 0 || (long long)(N1 - 1) < (long long)bs * nb))) return hipErrorInvalidValue;
     const long long n = rows * pitch;
     if (n <= 0) return hipSuccess;
     const unsigned blocks = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(round_table_kernel, dim3(blocks), dim3(256), 0, s, in, out, rows, N1, pitch, to_fp32,
-                       complex_out, bnd, nb);
+                       complex_out, bnd, nb, bs);
     return hipGetLastError();
 }
 
