@@ -897,11 +897,20 @@ constexpr bool use_split() {
     // 0.091 -> 0.085 ms once the stage twiddles sit in LDS; with them in
     // global memory the split rows had measured slower)
     constexpr bool fwd_rows = sizeof(R) == 4 && MODE == MODE_ROW && FK == FK_FWD && L >= 8192 && FS == 0;
-    return (Policy<R, L, MODE, FK, C>::split && ((FS & 7) != 4 || row_needs_split<R, L, MODE>())) || fwd_rows;
+    // plain complex64 rows of length 1024: 25 instead of 42 KiB per 2-wave
+    // workgroup, 12 instead of 6 waves per CU (3D N = 512: forward rows
+    // 0.614 -> 0.586 ms, inverse 0.615 -> 0.555 ms; 2D N = 512, whose 128 row
+    // tiles do not fill the chip anyway, +0.4 us).  Not the real-data rows
+    // (FS & 7 = 3, 4), whose pre- and post-processing reads the whole
+    // complex pencil from LDS.
+    constexpr bool rows1024 = sizeof(R) == 4 && MODE == MODE_ROW && (FK == FK_FWD || FK == FK_INV) && L == 1024 &&
+                              FS == 0;
+    return (Policy<R, L, MODE, FK, C>::split && ((FS & 7) != 4 || row_needs_split<R, L, MODE>())) || fwd_rows ||
+           rows1024;
 }
 template <typename R, int L, int MODE, int FK, int FS, int C = 0>
 constexpr int kernel_waves() {
-    if constexpr (!Policy<R, L, MODE, FK, C>::split && use_split<R, L, MODE, FK, FS, C>()) return 3;  // split forward rows
+    if constexpr (!Policy<R, L, MODE, FK, C>::split && use_split<R, L, MODE, FK, FS, C>()) return 3;  // split plain rows
     else return use_split<R, L, MODE, FK, FS, C>() ? Policy<R, L, MODE, FK, C>::min_waves : 1;
 }
 
@@ -922,6 +931,7 @@ __device__ __forceinline__ void tile_body(cplx<R>* v, cplx<R>* kt, cplx<R>* lds,
     cplx<R>* __restrict__ gout2 = reinterpret_cast<cplx<R>*>(p.out2);
     const R ks = (R)p.kscale;
     if constexpr (FK == FK_FWD && FSB == 3) {
+        static_assert(!SP, "the real-output post-processing reads whole complex values from LDS");
         run_from<R, L, C, NT, MODE, -1, F, 0, SP>(v, lds, t, tw);
         r2c_store<R, L, C, NT, F>(v, lds, gout, tl, p.out_se, t, reinterpret_cast<const cplx<R>*>(p.tw_big));
     } else if constexpr (FK == FK_FWD) {
