@@ -900,17 +900,20 @@ constexpr bool use_split() {
     // plain complex64 rows of length 1024: 25 instead of 42 KiB per 2-wave
     // workgroup, 12 instead of 6 waves per CU (3D N = 512: forward rows
     // 0.614 -> 0.586 ms, inverse 0.615 -> 0.555 ms; 2D N = 512, whose 128 row
-    // tiles do not fill the chip anyway, +0.4 us).  Not the real-data rows
-    // (FS & 7 = 3, 4), whose pre- and post-processing reads the whole
-    // complex pencil from LDS.
-    constexpr bool rows1024 = sizeof(R) == 4 && MODE == MODE_ROW && (FK == FK_FWD || FK == FK_INV) && L == 1024 &&
-                              FS == 0;
+    // tiles do not fill the chip anyway, +0.4 us); the two-output inverse
+    // rows of the gradient (256 VGPRs) 6 -> 8 waves per CU (3D N = 512
+    // gradient 12.95 -> 12.54 ms).  Not the real-data rows (FS & 7 = 3, 4),
+    // whose pre- and post-processing reads the whole complex pencil from LDS.
+    constexpr bool rows1024 = sizeof(R) == 4 && MODE == MODE_ROW && L == 1024 && FS == 0 &&
+                              (FK == FK_FWD || FK == FK_INV || FK == FK_INV_GRAD);
     return (Policy<R, L, MODE, FK, C>::split && ((FS & 7) != 4 || row_needs_split<R, L, MODE>())) || fwd_rows ||
            rows1024;
 }
 template <typename R, int L, int MODE, int FK, int FS, int C = 0>
 constexpr int kernel_waves() {
-    if constexpr (!Policy<R, L, MODE, FK, C>::split && use_split<R, L, MODE, FK, FS, C>()) return 3;  // split plain rows
+    // split plain rows (the two-output kind keeps its two spectra in registers)
+    if constexpr (!Policy<R, L, MODE, FK, C>::split && use_split<R, L, MODE, FK, FS, C>())
+        return FK == FK_INV_GRAD ? 2 : 3;
     else return use_split<R, L, MODE, FK, FS, C>() ? Policy<R, L, MODE, FK, C>::min_waves : 1;
 }
 
